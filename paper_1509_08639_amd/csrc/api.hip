@@ -1,0 +1,411 @@
+// Batch entry points of the C ABI: ym_mine, ym_mine_per_pair, ym_mine_device
+// and the parity entries ym_similarity / ym_nw_align.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "../../include/ymine.h"
+#include "ym_internal.h"
+#include "ym_runtime.h"
+
+using namespace ym;
+
+namespace {
+
+size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct HostBatchInfo {
+  int64_t n_src_sent = 0, n_tgt_sent = 0, n_src_tok = 0, n_tgt_tok = 0;
+};
+
+ym_status check_sent_off(const int64_t *o, int64_t n_sent, const char *what) {
+  if (!o) return fail(YM_EINVAL, "%s is NULL", what);
+  if (o[0] != 0) return fail(YM_EINVAL, "%s[0] must be 0", what);
+  for (int64_t s = 0; s < n_sent; s++)
+    if (o[s + 1] < o[s]) return fail(YM_EINVAL, "%s decreases at sentence %lld", what, (long long)s);
+  return YM_OK;
+}
+
+// Validate a host batch (pair table, sentence offsets, target sentence length limit).
+ym_status check_host_batch(const ym_batch *b, HostBatchInfo &info) {
+  if (!b) return fail(YM_EINVAL, "NULL batch");
+  if (b->n_pairs < 0) return fail(YM_EINVAL, "n_pairs < 0");
+  ym_status s;
+  if ((s = check_doc_off(b->src_doc_off, b->n_pairs, "src_doc_off"))) return s;
+  if ((s = check_doc_off(b->tgt_doc_off, b->n_pairs, "tgt_doc_off"))) return s;
+  info.n_src_sent = b->src_doc_off[b->n_pairs];
+  info.n_tgt_sent = b->tgt_doc_off[b->n_pairs];
+  if ((s = check_sent_off(b->src_sent_off, info.n_src_sent, "src_sent_off"))) return s;
+  if ((s = check_sent_off(b->tgt_sent_off, info.n_tgt_sent, "tgt_sent_off"))) return s;
+  info.n_src_tok = b->src_sent_off[info.n_src_sent];
+  info.n_tgt_tok = b->tgt_sent_off[info.n_tgt_sent];
+  if (info.n_src_tok > 0 && !b->src_tok) return fail(YM_EINVAL, "src_tok is NULL");
+  if (info.n_tgt_tok > 0 && !b->tgt_tok) return fail(YM_EINVAL, "tgt_tok is NULL");
+  for (int64_t s2 = 0; s2 < info.n_tgt_sent; s2++)
+    if (b->tgt_sent_off[s2 + 1] - b->tgt_sent_off[s2] > kTcap)
+      return fail(YM_EINVAL, "target sentence %lld has more than %d tokens", (long long)s2, kTcap);
+  return YM_OK;
+}
+
+// Copy a host batch into the context's input buffer.
+ym_status upload_batch(ym_ctx *c, const ym_batch *b, const HostBatchInfo &info, DevBatch &d) {
+  const size_t s1 = a256((size_t)(info.n_src_sent + 1) * 8), s2 = a256((size_t)(info.n_tgt_sent + 1) * 8);
+  const size_t s3 = a256((size_t)info.n_src_tok * 4 + 4), s4 = a256((size_t)info.n_tgt_tok * 4 + 4);
+  ym_status s = c->in.reserve(s1 + s2 + s3 + s4);
+  if (s) return s;
+  char *p = (char *)c->in.ptr;
+  d.src_sent_off = (const int64_t *)p;
+  d.tgt_sent_off = (const int64_t *)(p + s1);
+  d.src_tok = (const int32_t *)(p + s1 + s2);
+  d.tgt_tok = (const int32_t *)(p + s1 + s2 + s3);
+  d.n_src_sent = info.n_src_sent;
+  d.n_tgt_sent = info.n_tgt_sent;
+  d.n_src_tok = info.n_src_tok;
+  d.n_tgt_tok = info.n_tgt_tok;
+  hipError_t e;
+  if ((e = hipMemcpyAsync(p, b->src_sent_off, (size_t)(info.n_src_sent + 1) * 8, hipMemcpyHostToDevice, c->stream)) ||
+      (e = hipMemcpyAsync(p + s1, b->tgt_sent_off, (size_t)(info.n_tgt_sent + 1) * 8, hipMemcpyHostToDevice, c->stream)) ||
+      (info.n_src_tok &&
+       (e = hipMemcpyAsync(p + s1 + s2, b->src_tok, (size_t)info.n_src_tok * 4, hipMemcpyHostToDevice, c->stream))) ||
+      (info.n_tgt_tok &&
+       (e = hipMemcpyAsync(p + s1 + s2 + s3, b->tgt_tok, (size_t)info.n_tgt_tok * 4, hipMemcpyHostToDevice, c->stream))))
+    return hip_fail(e, "batch upload");
+  return YM_OK;
+}
+
+int64_t capacity_of(const int64_t *sdo, const int64_t *tdo, int64_t n_pairs) {
+  int64_t cap = 0;
+  for (int64_t p = 0; p < n_pairs; p++) cap += std::min(sdo[p + 1] - sdo[p], tdo[p + 1] - tdo[p]);
+  return cap;
+}
+
+size_t full_workspace(const int64_t *sdo, const int64_t *tdo, int64_t n_pairs) {
+  size_t b = 16 * 256;
+  for (int64_t p = 0; p < n_pairs; p++) b += pair_bytes(sdo[p + 1] - sdo[p], tdo[p + 1] - tdo[p]);
+  return b;
+}
+
+size_t min_workspace(const int64_t *sdo, const int64_t *tdo, int64_t n_pairs) {
+  size_t b = 0;
+  for (int64_t p = 0; p < n_pairs; p++) b = std::max(b, pair_bytes(sdo[p + 1] - sdo[p], tdo[p + 1] - tdo[p]));
+  return b + 16 * 256;
+}
+
+// Device output buffers of a host-API call, carved from ctx->outb.
+ym_status alloc_outputs(ym_ctx *c, int64_t n_pairs, int64_t cap, ym_device_out &o) {
+  const size_t s1 = a256((size_t)(n_pairs + 1) * 8), s2 = a256((size_t)std::max<int64_t>(n_pairs, 1) * 4);
+  const size_t s3 = a256((size_t)std::max<int64_t>(cap, 1) * 4);
+  ym_status s = c->outb.reserve(s1 + s2 + 3 * s3);
+  if (s) return s;
+  char *p = (char *)c->outb.ptr;
+  o.pair_off = (int64_t *)p;
+  o.align_score = (float *)(p + s1);
+  o.src_idx = (int32_t *)(p + s1 + s2);
+  o.tgt_idx = (int32_t *)(p + s1 + s2 + s3);
+  o.score = (float *)(p + s1 + s2 + 2 * s3);
+  return YM_OK;
+}
+
+// Copy device outputs into a freshly allocated ym_result.
+ym_status download_result(ym_ctx *c, int64_t n_pairs, const ym_device_out &o, ym_result **out) {
+  ym_result *r = (ym_result *)calloc(1, sizeof(ym_result));
+  if (!r) return fail(YM_ENOMEM, "result allocation");
+  r->n_pairs = n_pairs;
+  r->pair_off = (int64_t *)malloc((size_t)(n_pairs + 1) * 8);
+  r->align_score = (float *)malloc((size_t)std::max<int64_t>(n_pairs, 1) * 4);
+  if (!r->pair_off || !r->align_score) {
+    ym_result_free(r);
+    return fail(YM_ENOMEM, "result allocation");
+  }
+  hipError_t e = hipMemcpyAsync(r->pair_off, o.pair_off, (size_t)(n_pairs + 1) * 8, hipMemcpyDeviceToHost, c->stream);
+  if (!e && n_pairs) e = hipMemcpyAsync(r->align_score, o.align_score, (size_t)n_pairs * 4, hipMemcpyDeviceToHost, c->stream);
+  if (!e) e = hipStreamSynchronize(c->stream);
+  if (e) {
+    ym_result_free(r);
+    return hip_fail(e, "result download");
+  }
+  r->n_out = r->pair_off[n_pairs];
+  const size_t k = (size_t)std::max<int64_t>(r->n_out, 1);
+  r->src_idx = (int32_t *)malloc(k * 4);
+  r->tgt_idx = (int32_t *)malloc(k * 4);
+  r->score = (float *)malloc(k * 4);
+  if (!r->src_idx || !r->tgt_idx || !r->score) {
+    ym_result_free(r);
+    return fail(YM_ENOMEM, "result allocation");
+  }
+  if (r->n_out) {
+    e = hipMemcpyAsync(r->src_idx, o.src_idx, (size_t)r->n_out * 4, hipMemcpyDeviceToHost, c->stream);
+    if (!e) e = hipMemcpyAsync(r->tgt_idx, o.tgt_idx, (size_t)r->n_out * 4, hipMemcpyDeviceToHost, c->stream);
+    if (!e) e = hipMemcpyAsync(r->score, o.score, (size_t)r->n_out * 4, hipMemcpyDeviceToHost, c->stream);
+    if (!e) e = hipStreamSynchronize(c->stream);
+    if (e) {
+      ym_result_free(r);
+      return hip_fail(e, "result download");
+    }
+  }
+  *out = r;
+  return YM_OK;
+}
+
+// Shared driver of the host-batch entry points.
+enum class Mode { Batched, PerPair };
+
+ym_status mine_host(ym_ctx *c, const ym_lexicon *L, const ym_batch *b, const ym_params *prm, ym_result **out, Mode mode,
+                    float *S_host, int32_t *ms_host, int32_t *mt_host) {
+  if (!out && !S_host) return fail(YM_EINVAL, "NULL out");
+  if (out) *out = nullptr;
+  if (!c || !L) return fail(YM_EINVAL, "NULL context or lexicon");
+  ym_status s;
+  if ((s = check_params(prm))) return s;
+  HostBatchInfo info;
+  if ((s = check_host_batch(b, info))) return s;
+  const int64_t P = b->n_pairs;
+  hipSetDevice(c->device);
+  std::lock_guard<std::mutex> lk(c->mu);
+  DevBatch d;
+  if ((s = upload_batch(c, b, info, d))) return s;
+  const int64_t cap = capacity_of(b->src_doc_off, b->tgt_doc_off, P);
+  ym_device_out o;
+  if ((s = alloc_outputs(c, P, cap, o))) return s;
+  hipError_t e = hipMemsetAsync(o.pair_off, 0, 8, c->stream);
+  if (e) return hip_fail(e, "memset");
+  if ((s = ensure_table(c, prm, c->stream))) return s;
+
+  // debug S / m_s / m_t buffers (whole batch, device)
+  int64_t total_cells = 0;
+  for (int64_t p = 0; p < P; p++)
+    total_cells += (b->src_doc_off[p + 1] - b->src_doc_off[p]) * (b->tgt_doc_off[p + 1] - b->tgt_doc_off[p]);
+  DevBuf dbgbuf;
+  float *dS = nullptr;
+  int32_t *dms = nullptr, *dmt = nullptr;
+  if (S_host) {
+    const size_t cs = a256((size_t)std::max<int64_t>(total_cells, 1) * 4);
+    if ((s = dbgbuf.reserve(3 * cs))) return s;
+    dS = (float *)dbgbuf.ptr;
+    dms = (int32_t *)((char *)dbgbuf.ptr + cs);
+    dmt = (int32_t *)((char *)dbgbuf.ptr + 2 * cs);
+  }
+
+  std::vector<std::pair<int64_t, int64_t>> chunks;
+  if (mode == Mode::PerPair) {
+    for (int64_t p = 0; p < P; p++) chunks.push_back({p, p + 1});
+  } else {
+    const size_t full = full_workspace(b->src_doc_off, b->tgt_doc_off, P);
+    const size_t ws = std::max(std::min(full, c->arena_limit), min_workspace(b->src_doc_off, b->tgt_doc_off, P));
+    if ((s = plan_chunks(b->src_doc_off, b->tgt_doc_off, P, ws, chunks))) return s;
+  }
+  size_t need = 0;
+  std::vector<Chunk> lay(chunks.size());
+  for (size_t k = 0; k < chunks.size(); k++) {
+    lay[k].layout(b->src_doc_off, b->tgt_doc_off, chunks[k].first, chunks[k].second);
+    need = std::max(need, lay[k].bytes);
+  }
+  if ((s = c->ws.reserve(std::max<size_t>(need, 256)))) {
+    dbgbuf.release();
+    return s;
+  }
+  int64_t cell_base = 0;
+  for (size_t k = 0; k < chunks.size(); k++) {
+    DebugOut dbg;
+    const DebugOut *dp = nullptr;
+    if (S_host) {
+      dbg.S = dS + cell_base;
+      dbg.ms = dms + cell_base;
+      dbg.mt = dmt + cell_base;
+      dbg.sim_only = true;
+      dp = &dbg;
+    }
+    if ((s = run_chunk(c, L, d, prm, b->src_doc_off, b->tgt_doc_off, lay[k], (char *)c->ws.ptr, o, c->stream, dp))) {
+      hipStreamSynchronize(c->stream);
+      dbgbuf.release();
+      return s;
+    }
+    cell_base += lay[k].cells;
+    if (mode == Mode::PerPair && (e = hipStreamSynchronize(c->stream))) return hip_fail(e, "per-pair sync");
+  }
+  if (S_host) {
+    e = hipMemcpyAsync(S_host, dS, (size_t)total_cells * 4, hipMemcpyDeviceToHost, c->stream);
+    if (!e && ms_host) e = hipMemcpyAsync(ms_host, dms, (size_t)total_cells * 4, hipMemcpyDeviceToHost, c->stream);
+    if (!e && mt_host) e = hipMemcpyAsync(mt_host, dmt, (size_t)total_cells * 4, hipMemcpyDeviceToHost, c->stream);
+    if (!e) e = hipStreamSynchronize(c->stream);
+    dbgbuf.release();
+    if (e) return hip_fail(e, "similarity download");
+    return YM_OK;
+  }
+  return download_result(c, P, o, out);
+}
+
+}  // namespace
+
+extern "C" {
+
+void ym_result_free(ym_result *r) {
+  if (!r) return;
+  free(r->pair_off);
+  free(r->src_idx);
+  free(r->tgt_idx);
+  free(r->score);
+  free(r->align_score);
+  free(r);
+}
+
+ym_status ym_mine(ym_ctx *c, const ym_lexicon *L, const ym_batch *b, const ym_params *p, ym_result **out) {
+  return mine_host(c, L, b, p, out, Mode::Batched, nullptr, nullptr, nullptr);
+}
+
+ym_status ym_mine_per_pair(ym_ctx *c, const ym_lexicon *L, const ym_batch *b, const ym_params *p, ym_result **out) {
+  return mine_host(c, L, b, p, out, Mode::PerPair, nullptr, nullptr, nullptr);
+}
+
+ym_status ym_similarity(ym_ctx *c, const ym_lexicon *L, const ym_batch *b, const ym_params *p, float *S, int32_t *m_s,
+                        int32_t *m_t) {
+  if (!S) return fail(YM_EINVAL, "NULL S");
+  return mine_host(c, L, b, p, nullptr, Mode::Batched, S, m_s, m_t);
+}
+
+int64_t ym_mine_device_capacity(const int64_t *sdo, const int64_t *tdo, int64_t n_pairs) {
+  if (!sdo || !tdo || n_pairs < 0) return -1;
+  return capacity_of(sdo, tdo, n_pairs);
+}
+
+size_t ym_mine_device_workspace(const int64_t *sdo, const int64_t *tdo, int64_t n_pairs) {
+  if (!sdo || !tdo || n_pairs < 0) return 0;
+  return full_workspace(sdo, tdo, n_pairs);
+}
+
+size_t ym_mine_device_workspace_min(const int64_t *sdo, const int64_t *tdo, int64_t n_pairs) {
+  if (!sdo || !tdo || n_pairs < 0) return 0;
+  return min_workspace(sdo, tdo, n_pairs);
+}
+
+ym_status ym_mine_device(ym_ctx *c, const ym_lexicon *L, const ym_device_batch *b, const ym_params *prm, void *workspace,
+                         size_t workspace_bytes, const ym_device_out *out, void *stream) {
+  if (!c || !L || !b || !out) return fail(YM_EINVAL, "NULL argument");
+  ym_status s;
+  if ((s = check_params(prm))) return s;
+  if (b->n_pairs < 0) return fail(YM_EINVAL, "n_pairs < 0");
+  if ((s = check_doc_off(b->src_doc_off, b->n_pairs, "src_doc_off"))) return s;
+  if ((s = check_doc_off(b->tgt_doc_off, b->n_pairs, "tgt_doc_off"))) return s;
+  if (!out->pair_off || (b->n_pairs && !out->align_score)) return fail(YM_EINVAL, "NULL output array");
+  if (b->n_src_tok < 0 || b->n_tgt_tok < 0) return fail(YM_EINVAL, "negative token count");
+  if (!workspace && b->n_pairs) return fail(YM_EINVAL, "NULL workspace");
+  hipStream_t st = (hipStream_t)stream;
+  hipSetDevice(c->device);
+  std::lock_guard<std::mutex> lk(c->mu);
+  std::vector<std::pair<int64_t, int64_t>> chunks;
+  if ((s = plan_chunks(b->src_doc_off, b->tgt_doc_off, b->n_pairs, workspace_bytes, chunks))) return s;
+  if ((s = ensure_table(c, prm, st))) return s;
+  DevBatch d;
+  d.src_sent_off = b->src_sent_off;
+  d.tgt_sent_off = b->tgt_sent_off;
+  d.src_tok = b->src_tok;
+  d.tgt_tok = b->tgt_tok;
+  d.n_src_sent = b->src_doc_off[b->n_pairs];
+  d.n_tgt_sent = b->tgt_doc_off[b->n_pairs];
+  d.n_src_tok = b->n_src_tok;
+  d.n_tgt_tok = b->n_tgt_tok;
+  if (b->n_pairs == 0) {
+    hipError_t e = hipMemsetAsync(out->pair_off, 0, 8, st);
+    return e ? hip_fail(e, "memset") : YM_OK;
+  }
+  for (auto &ck : chunks) {
+    Chunk ch;
+    ch.layout(b->src_doc_off, b->tgt_doc_off, ck.first, ck.second);
+    if (ch.bytes > workspace_bytes) return fail(YM_ENOMEM, "workspace too small");
+    if ((s = run_chunk(c, L, d, prm, b->src_doc_off, b->tgt_doc_off, ch, (char *)workspace, *out, st, nullptr))) return s;
+  }
+  return YM_OK;
+}
+
+ym_status ym_nw_align(ym_ctx *c, const float *S, const int32_t *n, const int32_t *m, int64_t n_pairs, float gap,
+                      float threshold, float *align_score, char *moves, int32_t *n_moves, ym_result **out) {
+  if (out) *out = nullptr;
+  if (!c || !n || !m || n_pairs < 0) return fail(YM_EINVAL, "NULL argument");
+  if (!std::isfinite(gap) || !std::isfinite(threshold)) return fail(YM_EINVAL, "non-finite gap or threshold");
+  std::vector<int64_t> sdo(n_pairs + 1, 0), tdo(n_pairs + 1, 0);
+  int64_t cells = 0, mvlen = 0;
+  for (int64_t p = 0; p < n_pairs; p++) {
+    if (n[p] < 0 || m[p] < 0) return fail(YM_EINVAL, "negative size at pair %lld", (long long)p);
+    sdo[p + 1] = sdo[p] + n[p];
+    tdo[p + 1] = tdo[p] + m[p];
+    cells += (int64_t)n[p] * m[p];
+    mvlen += (int64_t)n[p] + m[p];
+  }
+  if (cells > 0 && !S) return fail(YM_EINVAL, "NULL S");
+  for (int64_t k = 0; k < cells; k++)
+    if (!std::isfinite(S[k])) return fail(YM_EINVAL, "non-finite score at %lld", (long long)k);
+  hipSetDevice(c->device);
+  std::lock_guard<std::mutex> lk(c->mu);
+  ym_status s;
+  const int64_t cap = capacity_of(sdo.data(), tdo.data(), n_pairs);
+  ym_device_out o;
+  if ((s = alloc_outputs(c, n_pairs, cap, o))) return s;
+  hipError_t e = hipMemsetAsync(o.pair_off, 0, 8, c->stream);
+  if (e) return hip_fail(e, "memset");
+  DevBuf buf;
+  const size_t cs = a256((size_t)std::max<int64_t>(cells, 1) * 4), ms = a256((size_t)std::max<int64_t>(mvlen, 1)),
+               ns = a256((size_t)std::max<int64_t>(n_pairs, 1) * 4);
+  if ((s = buf.reserve(cs + ms + ns))) return s;
+  float *dS = (float *)buf.ptr;
+  char *dmv = (char *)buf.ptr + cs;
+  int32_t *dnm = (int32_t *)((char *)buf.ptr + cs + ms);
+  if (cells && (e = hipMemcpyAsync(dS, S, (size_t)cells * 4, hipMemcpyHostToDevice, c->stream))) {
+    buf.release();
+    return hip_fail(e, "S upload");
+  }
+  std::vector<std::pair<int64_t, int64_t>> chunks;
+  const size_t full = full_workspace(sdo.data(), tdo.data(), n_pairs);
+  const size_t wsb = std::max(std::min(full, c->arena_limit), min_workspace(sdo.data(), tdo.data(), n_pairs));
+  if ((s = plan_chunks(sdo.data(), tdo.data(), n_pairs, wsb, chunks))) {
+    buf.release();
+    return s;
+  }
+  std::vector<Chunk> lay(chunks.size());
+  size_t need = 256;
+  for (size_t k = 0; k < chunks.size(); k++) {
+    lay[k].layout(sdo.data(), tdo.data(), chunks[k].first, chunks[k].second);
+    need = std::max(need, lay[k].bytes);
+  }
+  if ((s = c->ws.reserve(need))) {
+    buf.release();
+    return s;
+  }
+  ym_params prm;
+  std::memset(&prm, 0, sizeof prm);
+  prm.gap = gap;
+  prm.threshold = threshold;
+  DevBatch d;
+  std::memset(&d, 0, sizeof d);
+  int64_t cell_base = 0, mv_base = 0;
+  for (size_t k = 0; k < chunks.size(); k++) {
+    DebugOut dbg;
+    dbg.S = dS + cell_base;
+    dbg.S_given = true;
+    dbg.moves_dev = dmv;
+    dbg.moves_base = mv_base;
+    dbg.n_moves_dev = dnm;
+    if ((s = run_chunk(c, nullptr, d, &prm, sdo.data(), tdo.data(), lay[k], (char *)c->ws.ptr, o, c->stream, &dbg))) {
+      hipStreamSynchronize(c->stream);
+      buf.release();
+      return s;
+    }
+    cell_base += lay[k].cells;
+    for (int64_t p = lay[k].p0; p < lay[k].p1; p++) mv_base += (int64_t)n[p] + m[p];
+  }
+  if (align_score && n_pairs)
+    e = hipMemcpyAsync(align_score, o.align_score, (size_t)n_pairs * 4, hipMemcpyDeviceToHost, c->stream);
+  if (!e && moves && mvlen) e = hipMemcpyAsync(moves, dmv, (size_t)mvlen, hipMemcpyDeviceToHost, c->stream);
+  if (!e && n_moves && n_pairs) e = hipMemcpyAsync(n_moves, dnm, (size_t)n_pairs * 4, hipMemcpyDeviceToHost, c->stream);
+  if (!e) e = hipStreamSynchronize(c->stream);
+  buf.release();
+  if (e) return hip_fail(e, "nw download");
+  if (out) return download_result(c, n_pairs, o, out);
+  return YM_OK;
+}
+
+}  // extern "C"

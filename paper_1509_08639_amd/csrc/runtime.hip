@@ -1,0 +1,526 @@
+// Host runtime and C ABI of libymine (declared in include/ymine.h).
+//
+// Contexts own a HIP stream and a device arena; lexicons are normalised on the
+// host (sort, merge duplicate keys, deduplicate targets) and inserted into an
+// HBM hash table by a kernel.  A batch is planned on the host from its pair
+// table (per-pair offsets of the score block, output slots and, for pairs too
+// large for LDS, global scratch), split into chunks that fit the workspace,
+// and each chunk runs: similarity kernel -> NW kernel (forward, traceback,
+// threshold) -> scan -> compaction.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/ymine.h"
+#include "ym_internal.h"
+#include "ym_runtime.h"
+
+using namespace ym;
+
+namespace {
+thread_local std::string g_err;
+}
+
+namespace ym {
+
+ym_status fail(ym_status code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+ym_status hip_fail(hipError_t e, const char *what) {
+  return fail(YM_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// ------------------------------------------------------------ device buffer
+ym_status DevBuf::reserve(size_t bytes) {
+  if (bytes <= cap) return YM_OK;
+  if (ptr) hipFree(ptr);
+  ptr = nullptr;
+  cap = 0;
+  size_t want = std::max(bytes, cap * 3 / 2);
+  hipError_t e = hipMalloc(&ptr, want);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    e = hipMalloc(&ptr, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      ptr = nullptr;
+      return fail(YM_ENOMEM, "hipMalloc(%zu) failed", bytes);
+    }
+    want = bytes;
+  }
+  cap = want;
+  return YM_OK;
+}
+
+void DevBuf::release() {
+  if (ptr) hipFree(ptr);
+  ptr = nullptr;
+  cap = 0;
+}
+
+ym_status HostBuf::reserve(size_t bytes) {
+  if (bytes <= cap) return YM_OK;
+  if (ptr) hipHostFree(ptr);
+  ptr = nullptr;
+  cap = 0;
+  size_t want = std::max(bytes, size_t(1) << 20);
+  hipError_t e = hipHostMalloc(&ptr, want, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    ptr = nullptr;
+    return fail(YM_ENOMEM, "hipHostMalloc(%zu) failed", want);
+  }
+  cap = want;
+  return YM_OK;
+}
+
+void HostBuf::release() {
+  if (ptr) hipHostFree(ptr);
+  ptr = nullptr;
+  cap = 0;
+}
+
+// ------------------------------------------------------------------ plan
+// Per-pair requirement in workspace bytes (score block, scratch, slots).
+static inline bool nw_needs_global_dirs(int64_t n, int64_t m) { return n * ((m + 15) / 16) > kDirLds; }
+static inline bool nw_needs_global_row(int64_t n, int64_t m) { return n > 64 && m + 1 > kRowLds; }
+
+size_t pair_bytes(int64_t n, int64_t m) {
+  size_t b = sizeof(PairDesc) + 4 /*count*/ + 8 /*moves off*/;
+  b += (size_t)((n + kItemRows - 1) / kItemRows) * sizeof(SimItem);
+  b += (size_t)(n * m) * 4;
+  if (nw_needs_global_dirs(n, m)) b += (size_t)(n * ((m + 15) / 16)) * 4;
+  if (nw_needs_global_row(n, m)) b += (size_t)(m + 1) * 4;
+  b += (size_t)std::min(n, m) * 12;
+  return b;
+}
+
+static const size_t kChunkSlack = 16 * 256;  // alignment padding of the regions
+
+ym_status Chunk::layout(const int64_t *sdo, const int64_t *tdo, int64_t p0_, int64_t p1_) {
+  p0 = p0_;
+  p1 = p1_;
+  np = p1 - p0;
+  n_items = 0;
+  cells = 0;
+  dir_words = 0;
+  row_floats = 0;
+  slots = 0;
+  for (int64_t p = p0; p < p1; p++) {
+    const int64_t n = sdo[p + 1] - sdo[p], m = tdo[p + 1] - tdo[p];
+    if (n > 0 && m > 0) n_items += (n + kItemRows - 1) / kItemRows;
+    cells += n * m;
+    if (nw_needs_global_dirs(n, m)) dir_words += n * ((m + 15) / 16);
+    if (nw_needs_global_row(n, m)) row_floats += m + 1;
+    slots += std::min(n, m);
+  }
+  size_t o = 0;
+  off_descs = o;
+  o = align256(o + (size_t)np * sizeof(PairDesc));
+  off_items = o;
+  o = align256(o + (size_t)std::max<int64_t>(n_items, 1) * sizeof(SimItem));
+  off_S = o;
+  o = align256(o + (size_t)cells * 4);
+  off_dirs = o;
+  o = align256(o + (size_t)dir_words * 4);
+  off_rows = o;
+  o = align256(o + (size_t)row_floats * 4);
+  off_ssrc = o;
+  o = align256(o + (size_t)slots * 4);
+  off_stgt = o;
+  o = align256(o + (size_t)slots * 4);
+  off_sscore = o;
+  o = align256(o + (size_t)slots * 4);
+  off_counts = o;
+  o = align256(o + (size_t)np * 4);
+  off_moves_off = o;
+  o = align256(o + (size_t)np * 8);
+  bytes = o;
+  host_bytes = align256((size_t)np * sizeof(PairDesc)) + align256((size_t)std::max<int64_t>(n_items, 1) * sizeof(SimItem)) +
+               align256((size_t)np * 8);
+  return YM_OK;
+}
+
+// Fill descriptors / items / move offsets into pinned host memory.
+void Chunk::fill_host(const int64_t *sdo, const int64_t *tdo, char *host) const {
+  PairDesc *descs = (PairDesc *)host;
+  SimItem *items = (SimItem *)(host + align256((size_t)np * sizeof(PairDesc)));
+  int64_t *moff = (int64_t *)(host + align256((size_t)np * sizeof(PairDesc)) +
+                              align256((size_t)std::max<int64_t>(n_items, 1) * sizeof(SimItem)));
+  int64_t s_off = 0, out_off = 0, dir_off = 0, row_off = 0, mv = 0, it = 0;
+  for (int64_t p = p0; p < p1; p++) {
+    const int64_t n = sdo[p + 1] - sdo[p], m = tdo[p + 1] - tdo[p];
+    PairDesc &d = descs[p - p0];
+    d.src_sent0 = sdo[p];
+    d.tgt_sent0 = tdo[p];
+    d.s_off = s_off;
+    d.out_off = out_off;
+    d.n = (int32_t)n;
+    d.m = (int32_t)m;
+    if (nw_needs_global_dirs(n, m)) {
+      d.dir_off = dir_off;
+      dir_off += n * ((m + 15) / 16);
+    } else {
+      d.dir_off = -1;
+    }
+    if (nw_needs_global_row(n, m)) {
+      d.row_off = row_off;
+      row_off += m + 1;
+    } else {
+      d.row_off = -1;
+    }
+    if (n > 0 && m > 0)
+      for (int64_t i0 = 0; i0 < n; i0 += kItemRows) {
+        SimItem &x = items[it++];
+        x.pair = (int32_t)(p - p0);
+        x.i0 = (int32_t)i0;
+        x.i1 = (int32_t)std::min<int64_t>(n, i0 + kItemRows);
+        x.pad = 0;
+      }
+    moff[p - p0] = mv;
+    mv += n + m;
+    s_off += n * m;
+    out_off += std::min(n, m);
+  }
+}
+
+}  // namespace ym
+
+// =================================================================== ABI
+struct ym_lexicon {
+  ym_ctx *ctx = nullptr;
+  int4 *slots = nullptr;
+  int32_t *vals = nullptr;
+  uint32_t mask = 0;
+  int32_t shift = 0;
+  int64_t n_keys = 0, n_pairs = 0;
+  int32_t max_fanout = 0;
+};
+
+extern "C" {
+
+const char *ym_last_error(void) { return g_err.c_str(); }
+
+const char *ym_version(void) { return "ymine 0.1 (gfx950)"; }
+
+ym_status ym_create(int device, size_t hbm_budget_bytes, ym_ctx **out) {
+  if (!out) return fail(YM_EINVAL, "out is NULL");
+  *out = nullptr;
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || ndev <= 0) return fail(YM_EDEVICE, "no HIP device available");
+  if (device < 0 || device >= ndev) return fail(YM_EINVAL, "device %d out of range (%d devices)", device, ndev);
+  if ((e = hipSetDevice(device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+  ym_ctx *c = new (std::nothrow) ym_ctx();
+  if (!c) return fail(YM_ENOMEM, "context allocation");
+  c->device = device;
+  if ((e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking)) != hipSuccess) {
+    delete c;
+    return hip_fail(e, "hipStreamCreate");
+  }
+  if ((e = hipEventCreateWithFlags(&c->staging_done, hipEventDisableTiming)) != hipSuccess) {
+    hipStreamDestroy(c->stream);
+    delete c;
+    return hip_fail(e, "hipEventCreate");
+  }
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = total_b = 0;
+  c->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.8 * (double)free_b);
+  c->arena_limit = std::max<size_t>((size_t)1 << 30, std::min<size_t>((size_t)(0.25 * (double)free_b), (size_t)16 << 30));
+  *out = c;
+  return YM_OK;
+}
+
+void ym_destroy(ym_ctx *c) {
+  if (!c) return;
+  hipSetDevice(c->device);
+  hipStreamSynchronize(c->stream);
+  c->table.release();
+  c->in.release();
+  c->ws.release();
+  c->outb.release();
+  c->staging.release();
+  c->host_out.release();
+  hipEventDestroy(c->staging_done);
+  hipStreamDestroy(c->stream);
+  delete c;
+}
+
+ym_status ym_lexicon_load(ym_ctx *c, const int32_t *src_ids, const int64_t *off, const int32_t *tgt_ids, int64_t n_src,
+                          ym_lexicon **out) {
+  if (!c || !out) return fail(YM_EINVAL, "NULL context or out");
+  *out = nullptr;
+  if (n_src < 0) return fail(YM_EINVAL, "n_src < 0");
+  if (n_src > 0 && (!src_ids || !off)) return fail(YM_EINVAL, "NULL lexicon arrays");
+  if (n_src > 0 && off[0] != 0) return fail(YM_EINVAL, "off[0] must be 0");
+  for (int64_t e = 0; e < n_src; e++) {
+    if (off[e + 1] < off[e]) return fail(YM_EINVAL, "lexicon offsets decrease at entry %lld", (long long)e);
+    if (src_ids[e] < 0) return fail(YM_EINVAL, "negative source id at entry %lld", (long long)e);
+  }
+  const int64_t total = n_src > 0 ? off[n_src] : 0;
+  if (total > 0 && !tgt_ids) return fail(YM_EINVAL, "NULL tgt_ids");
+  if (total >= ((int64_t)1 << 31)) return fail(YM_EINVAL, "lexicon holds 2^31 or more translation pairs");
+  for (int64_t v = 0; v < total; v++)
+    if (tgt_ids[v] < 0) return fail(YM_EINVAL, "negative target id at value %lld", (long long)v);
+
+  // normalise: sort (key, target), drop duplicates
+  std::vector<uint64_t> pr;
+  try {
+    pr.resize((size_t)total);
+  } catch (...) {
+    return fail(YM_ENOMEM, "host memory for lexicon");
+  }
+  int64_t k = 0;
+  for (int64_t e = 0; e < n_src; e++)
+    for (int64_t v = off[e]; v < off[e + 1]; v++) pr[k++] = ((uint64_t)(uint32_t)src_ids[e] << 32) | (uint32_t)tgt_ids[v];
+  std::sort(pr.begin(), pr.end());
+  pr.erase(std::unique(pr.begin(), pr.end()), pr.end());
+  std::vector<int32_t> keys, cnts, vals(pr.size());
+  std::vector<int64_t> offs;
+  int32_t maxf = 0;
+  for (size_t e = 0; e < pr.size(); e++) {
+    const int32_t key = (int32_t)(pr[e] >> 32);
+    vals[e] = (int32_t)(uint32_t)pr[e];
+    if (keys.empty() || keys.back() != key) {
+      keys.push_back(key);
+      cnts.push_back(0);
+      offs.push_back((int64_t)e);
+    }
+    cnts.back()++;
+    maxf = std::max(maxf, cnts.back());
+  }
+  if (maxf > YM_MAX_FANOUT) return fail(YM_EINVAL, "a key has %d targets (max %d)", maxf, YM_MAX_FANOUT);
+
+  ym_lexicon *L = new (std::nothrow) ym_lexicon();
+  if (!L) return fail(YM_ENOMEM, "lexicon allocation");
+  L->ctx = c;
+  L->n_keys = (int64_t)keys.size();
+  L->n_pairs = (int64_t)vals.size();
+  L->max_fanout = maxf;
+  int lg = 10;
+  while (((int64_t)1 << lg) < 2 * std::max<int64_t>(L->n_keys, 1)) lg++;
+  const int64_t cap = (int64_t)1 << lg;
+  L->mask = (uint32_t)(cap - 1);
+  L->shift = 32 - lg;
+
+  hipSetDevice(c->device);
+  std::lock_guard<std::mutex> lk(c->mu);
+  hipError_t e;
+  void *dkeys = nullptr, *dcnts = nullptr, *doffs = nullptr;
+  auto cleanup = [&]() {
+    if (dkeys) hipFree(dkeys);
+    if (dcnts) hipFree(dcnts);
+    if (doffs) hipFree(doffs);
+  };
+  if ((e = hipMalloc(&L->slots, (size_t)cap * sizeof(int4))) != hipSuccess ||
+      (e = hipMalloc(&L->vals, std::max<size_t>(vals.size(), 1) * 4)) != hipSuccess ||
+      (e = hipMalloc(&dkeys, std::max<size_t>(keys.size(), 1) * 4)) != hipSuccess ||
+      (e = hipMalloc(&dcnts, std::max<size_t>(keys.size(), 1) * 4)) != hipSuccess ||
+      (e = hipMalloc(&doffs, std::max<size_t>(keys.size(), 1) * 8)) != hipSuccess) {
+    (void)hipGetLastError();
+    cleanup();
+    if (L->slots) hipFree(L->slots);
+    if (L->vals) hipFree(L->vals);
+    delete L;
+    return fail(YM_ENOMEM, "device memory for lexicon");
+  }
+  e = hipMemsetAsync(L->slots, 0xFF, (size_t)cap * sizeof(int4), c->stream);  // keys = -1 (empty)
+  if (e == hipSuccess && !vals.empty())
+    e = hipMemcpyAsync(L->vals, vals.data(), vals.size() * 4, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess && !keys.empty()) e = hipMemcpyAsync(dkeys, keys.data(), keys.size() * 4, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess && !keys.empty()) e = hipMemcpyAsync(dcnts, cnts.data(), keys.size() * 4, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess && !keys.empty()) e = hipMemcpyAsync(doffs, offs.data(), keys.size() * 8, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess)
+    e = launch_lex_insert((const int32_t *)dkeys, (const int32_t *)dcnts, (const int64_t *)doffs, (int64_t)keys.size(),
+                          L->slots, L->mask, L->shift, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  cleanup();
+  if (e != hipSuccess) {
+    hipFree(L->slots);
+    hipFree(L->vals);
+    delete L;
+    return hip_fail(e, "lexicon upload");
+  }
+  *out = L;
+  return YM_OK;
+}
+
+void ym_lexicon_free(ym_lexicon *L) {
+  if (!L) return;
+  if (L->ctx) {
+    hipSetDevice(L->ctx->device);
+    hipStreamSynchronize(L->ctx->stream);
+  }
+  hipFree(L->slots);
+  hipFree(L->vals);
+  delete L;
+}
+
+ym_status ym_lexicon_stats(const ym_lexicon *L, int64_t *n_keys, int64_t *n_pairs, int32_t *max_fanout) {
+  if (!L) return fail(YM_EINVAL, "NULL lexicon");
+  if (n_keys) *n_keys = L->n_keys;
+  if (n_pairs) *n_pairs = L->n_pairs;
+  if (max_fanout) *max_fanout = L->max_fanout;
+  return YM_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------- shared internals
+namespace ym {
+
+LexDev lex_dev(const ym_lexicon *L) {
+  LexDev d;
+  d.slots = L->slots;
+  d.vals = L->vals;
+  d.mask = L->mask;
+  d.shift = L->shift;
+  return d;
+}
+
+ym_status check_params(const ym_params *p) {
+  if (!p) return fail(YM_EINVAL, "NULL params");
+  for (int k = 0; k < 4; k++)
+    if (!std::isfinite(p->w[k])) return fail(YM_EINVAL, "weight %d is not finite", k);
+  if (!std::isfinite(p->gap)) return fail(YM_EINVAL, "gap is not finite");
+  if (!std::isfinite(p->threshold)) return fail(YM_EINVAL, "threshold is not finite");
+  return YM_OK;
+}
+
+// Make sure the score table matches the weights (rebuilt on change).
+ym_status ensure_table(ym_ctx *c, const ym_params *p, hipStream_t st) {
+  if (c->table_valid && std::memcmp(c->table_w, p->w, sizeof c->table_w) == 0) return YM_OK;
+  ym_status s = c->table.reserve((size_t)kTabLen * kTabLen * kTabLen * kTabLen * 4);
+  if (s) return s;
+  hipError_t e = launch_score_table(p->w[0], p->w[1], p->w[2], p->w[3], (float *)c->table.ptr, st);
+  if (e != hipSuccess) return hip_fail(e, "score table");
+  std::memcpy(c->table_w, p->w, sizeof c->table_w);
+  c->table_valid = true;
+  return YM_OK;
+}
+
+// Validate a host pair table: offsets start at 0 and never decrease.
+ym_status check_doc_off(const int64_t *o, int64_t n_pairs, const char *what) {
+  if (!o) return fail(YM_EINVAL, "%s is NULL", what);
+  if (o[0] != 0) return fail(YM_EINVAL, "%s[0] must be 0", what);
+  for (int64_t p = 0; p < n_pairs; p++) {
+    if (o[p + 1] < o[p]) return fail(YM_EINVAL, "%s decreases at pair %lld", what, (long long)p);
+    if (o[p + 1] - o[p] > 0x7fffffffLL) return fail(YM_EINVAL, "%s: pair %lld has 2^31 sentences or more", what, (long long)p);
+  }
+  return YM_OK;
+}
+
+// Split pairs [0, n_pairs) into chunks whose workspace fits `ws_bytes`.
+ym_status plan_chunks(const int64_t *sdo, const int64_t *tdo, int64_t n_pairs, size_t ws_bytes,
+                      std::vector<std::pair<int64_t, int64_t>> &chunks) {
+  chunks.clear();
+  int64_t p = 0;
+  while (p < n_pairs) {
+    size_t acc = kChunkSlack;
+    int64_t q = p;
+    while (q < n_pairs) {
+      const size_t b = pair_bytes(sdo[q + 1] - sdo[q], tdo[q + 1] - tdo[q]);
+      if (q > p && acc + b > ws_bytes) break;
+      acc += b;
+      q++;
+    }
+    if (acc > ws_bytes) return fail(YM_ENOMEM, "pair %lld needs %zu workspace bytes, %zu given", (long long)p, acc, ws_bytes);
+    chunks.push_back({p, q});
+    p = q;
+  }
+  return YM_OK;
+}
+
+// Enqueue one chunk: upload its plan, then the four kernels.
+ym_status run_chunk(ym_ctx *c, const ym_lexicon *L, const DevBatch &b, const ym_params *prm, const int64_t *sdo,
+                    const int64_t *tdo, const Chunk &ch, char *ws, const ym_device_out &out, hipStream_t st,
+                    const DebugOut *dbg) {
+  // plan -> pinned staging -> workspace (wait for the previous upload to have left the staging buffer)
+  hipError_t e = hipEventSynchronize(c->staging_done);
+  if (e != hipSuccess) return hip_fail(e, "staging wait");
+  ym_status s = c->staging.reserve(ch.host_bytes);
+  if (s) return s;
+  ch.fill_host(sdo, tdo, (char *)c->staging.ptr);
+  const size_t dsz = align256((size_t)ch.np * sizeof(PairDesc));
+  const size_t isz = align256((size_t)std::max<int64_t>(ch.n_items, 1) * sizeof(SimItem));
+  const char *hp = (const char *)c->staging.ptr;
+  if ((e = hipMemcpyAsync(ws + ch.off_descs, hp, dsz, hipMemcpyHostToDevice, st)) != hipSuccess ||
+      (e = hipMemcpyAsync(ws + ch.off_items, hp + dsz, isz, hipMemcpyHostToDevice, st)) != hipSuccess ||
+      (e = hipMemcpyAsync(ws + ch.off_moves_off, hp + dsz + isz, align256((size_t)ch.np * 8), hipMemcpyHostToDevice, st)) !=
+          hipSuccess ||
+      (e = hipEventRecord(c->staging_done, st)) != hipSuccess)
+    return hip_fail(e, "plan upload");
+
+  const PairDesc *descs = (const PairDesc *)(ws + ch.off_descs);
+  float *S = dbg && dbg->S ? dbg->S : (float *)(ws + ch.off_S);
+  if (!(dbg && dbg->S_given)) {
+    SimArgs a;
+    a.items = (const SimItem *)(ws + ch.off_items);
+    a.n_items = ch.n_items;
+    a.descs = descs;
+    a.src_sent_off = b.src_sent_off;
+    a.src_tok = b.src_tok;
+    a.tgt_sent_off = b.tgt_sent_off;
+    a.tgt_tok = b.tgt_tok;
+    a.n_src_sent = b.n_src_sent;
+    a.n_tgt_sent = b.n_tgt_sent;
+    a.n_src_tok = b.n_src_tok;
+    a.n_tgt_tok = b.n_tgt_tok;
+    a.lex = lex_dev(L);
+    a.w0 = prm->w[0];
+    a.w1 = prm->w[1];
+    a.w2 = prm->w[2];
+    a.w3 = prm->w[3];
+    a.table = (const float *)c->table.ptr;
+    a.S = S;
+    a.ms_out = dbg ? dbg->ms : nullptr;
+    a.mt_out = dbg ? dbg->mt : nullptr;
+    const int grid = (int)std::min<int64_t>(ch.n_items, (int64_t)1 << 30);
+    if ((e = launch_similarity(a, grid, st)) != hipSuccess) return hip_fail(e, "similarity kernel");
+    if (dbg && dbg->sim_only) return YM_OK;
+  }
+  NwArgs n;
+  n.descs = descs;
+  n.n_pairs = ch.np;
+  n.S = S;
+  n.gap = prm->gap;
+  n.tau = prm->threshold;
+  n.dir_scratch = (uint32_t *)(ws + ch.off_dirs);
+  n.row_scratch = (float *)(ws + ch.off_rows);
+  n.slot_src = (int32_t *)(ws + ch.off_ssrc);
+  n.slot_tgt = (int32_t *)(ws + ch.off_stgt);
+  n.slot_score = (float *)(ws + ch.off_sscore);
+  n.counts = (int32_t *)(ws + ch.off_counts);
+  n.align = out.align_score;
+  n.pair_base = ch.p0;
+  n.moves = dbg ? dbg->moves_dev : nullptr;
+  n.moves_off = (const int64_t *)(ws + ch.off_moves_off);
+  n.n_moves = dbg ? dbg->n_moves_dev : nullptr;
+  if (n.moves) n.moves += dbg->moves_base;
+  if ((e = launch_nw(n, st)) != hipSuccess) return hip_fail(e, "nw kernel");
+  if ((e = launch_scan(n.counts, ch.np, out.pair_off + ch.p0, ch.p0 == 0, st)) != hipSuccess) return hip_fail(e, "scan");
+  if ((e = launch_compact(descs, ch.np, n.counts, out.pair_off + ch.p0, n.slot_src, n.slot_tgt, n.slot_score, out.src_idx,
+                          out.tgt_idx, out.score, st)) != hipSuccess)
+    return hip_fail(e, "compact");
+  return YM_OK;
+}
+
+}  // namespace ym

@@ -1,0 +1,104 @@
+// Internal definitions shared by the kernels and the host runtime of libymine.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ym {
+
+constexpr int32_t kEmpty = -1;          // empty hash slot key (lexicon ids are >= 0)
+constexpr uint32_t kHitBit = 0x80000000u;  // "target id is in X_i" flag of a mask word
+constexpr int kPosBits = 31;            // source positions per mask pass
+
+// Similarity kernel tiling.
+constexpr int kSimThreads = 256;        // 4 waves; each wave owns one source sentence at a time
+constexpr int kSimWaves = kSimThreads / 64;
+constexpr int kTcap = 1024;             // max target tokens staged per chunk (and per sentence)
+constexpr int kUcap = 2 * kTcap;        // LDS hash slots for the chunk's distinct target ids
+constexpr int kLogUcap = 11;
+constexpr int kJcap = 256;              // max target sentences per chunk
+constexpr int kJpass = kJcap / 64;      // target-sentence passes of one wave
+constexpr int kItemRows = 128;          // source sentences per work item
+constexpr int kTabLen = 32;             // score table covers sentence lengths < 32
+
+// NW kernel staging.
+constexpr int kDirLds = 2688;           // direction words held in LDS (covers 200 x 200)
+constexpr int kRowLds = 512;            // boundary-row floats held in LDS
+
+static_assert((1 << kLogUcap) == kUcap, "hash capacity");
+
+// One document pair of a chunk.
+struct PairDesc {
+  int64_t src_sent0;  // global index of its first source sentence
+  int64_t tgt_sent0;  // global index of its first target sentence
+  int64_t s_off;      // offset of its n x m score block (floats)
+  int64_t out_off;    // offset of its min(n, m) output slots
+  int64_t dir_off;    // offset of its direction words in global scratch (-1: LDS)
+  int64_t row_off;    // offset of its boundary row in global scratch (-1: LDS)
+  int32_t n, m;
+};
+
+// Similarity work item: source sentences [i0, i1) of pair `pair` against all
+// its target sentences.
+struct SimItem {
+  int32_t pair;
+  int32_t i0, i1;
+  int32_t pad;
+};
+
+// Lexicon as resident in HBM: open-addressing table of {key, count, offset, 0}
+// slots (linear probing, load <= 1/2) over a CSR value array.
+struct LexDev {
+  const int4 *slots;
+  const int32_t *vals;
+  uint32_t mask;
+  int32_t shift;
+};
+
+struct SimArgs {
+  const SimItem *items;
+  int64_t n_items;
+  const PairDesc *descs;
+  const int64_t *src_sent_off;
+  const int32_t *src_tok;
+  const int64_t *tgt_sent_off;
+  const int32_t *tgt_tok;
+  int64_t n_src_sent, n_tgt_sent, n_src_tok, n_tgt_tok;
+  LexDev lex;
+  float w0, w1, w2, w3;
+  const float *table;  // kTabLen^4 scores for short sentences
+  float *S;
+  int32_t *ms_out;  // optional
+  int32_t *mt_out;  // optional
+};
+
+struct NwArgs {
+  const PairDesc *descs;
+  int64_t n_pairs;
+  const float *S;
+  float gap, tau;
+  uint32_t *dir_scratch;
+  float *row_scratch;
+  int32_t *slot_src, *slot_tgt;
+  float *slot_score;
+  int32_t *counts;      // [n_pairs] accepted pairs
+  float *align;         // [n_pairs] H[n][m] (global pair index = pair_base + local)
+  int64_t pair_base;
+  char *moves;          // optional: forward paths
+  const int64_t *moves_off;  // [n_pairs] (local) offsets into moves
+  int32_t *n_moves;     // optional [n_pairs] (global index)
+};
+
+// Launch wrappers (kernels.hip).
+hipError_t launch_lex_insert(const int32_t *keys, const int32_t *cnts, const int64_t *offs, int64_t n, int4 *slots,
+                             uint32_t mask, int shift, hipStream_t st);
+hipError_t launch_score_table(float w0, float w1, float w2, float w3, float *table, hipStream_t st);
+hipError_t launch_similarity(const SimArgs &a, int grid, hipStream_t st);
+hipError_t launch_nw(const NwArgs &a, hipStream_t st);
+hipError_t launch_scan(const int32_t *counts, int64_t n, int64_t *pair_off_at_p0, int first, hipStream_t st);
+hipError_t launch_compact(const PairDesc *descs, int64_t n_pairs, const int32_t *counts, const int64_t *pair_off_at_p0,
+                          const int32_t *slot_src, const int32_t *slot_tgt, const float *slot_score, int32_t *out_src,
+                          int32_t *out_tgt, float *out_score, hipStream_t st);
+hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st);
+
+}  // namespace ym

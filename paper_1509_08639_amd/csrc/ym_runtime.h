@@ -1,0 +1,82 @@
+// Host-side runtime structures of libymine (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <mutex>
+#include <utility>
+#include <vector>
+
+#include "../../include/ymine.h"
+#include "ym_internal.h"
+
+namespace ym {
+
+struct DevBuf {
+  void *ptr = nullptr;
+  size_t cap = 0;
+  ym_status reserve(size_t bytes);
+  void release();
+};
+
+struct HostBuf {  // pinned
+  void *ptr = nullptr;
+  size_t cap = 0;
+  ym_status reserve(size_t bytes);
+  void release();
+};
+
+// Device view of a batch (all pointers on the device).
+struct DevBatch {
+  const int64_t *src_sent_off, *tgt_sent_off;
+  const int32_t *src_tok, *tgt_tok;
+  int64_t n_src_sent, n_tgt_sent, n_src_tok, n_tgt_tok;
+};
+
+// Optional debug outputs of a chunk run.
+struct DebugOut {
+  float *S = nullptr;        // if set: score matrices go here (device, chunk-local layout)
+  bool S_given = false;      // S already holds the scores: skip the similarity kernel
+  bool sim_only = false;     // stop after the similarity kernel
+  int32_t *ms = nullptr, *mt = nullptr;
+  char *moves_dev = nullptr; // device buffer for paths
+  int64_t moves_base = 0;    // offset of this chunk's first pair in moves_dev
+  int32_t *n_moves_dev = nullptr;
+};
+
+// Workspace layout of one chunk of pairs [p0, p1).
+struct Chunk {
+  int64_t p0 = 0, p1 = 0, np = 0, n_items = 0, cells = 0, dir_words = 0, row_floats = 0, slots = 0;
+  size_t off_descs = 0, off_items = 0, off_S = 0, off_dirs = 0, off_rows = 0, off_ssrc = 0, off_stgt = 0,
+         off_sscore = 0, off_counts = 0, off_moves_off = 0, bytes = 0, host_bytes = 0;
+  ym_status layout(const int64_t *sdo, const int64_t *tdo, int64_t p0, int64_t p1);
+  void fill_host(const int64_t *sdo, const int64_t *tdo, char *host) const;
+};
+
+ym_status fail(ym_status code, const char *fmt, ...);
+ym_status hip_fail(hipError_t e, const char *what);
+size_t pair_bytes(int64_t n, int64_t m);
+LexDev lex_dev(const ym_lexicon *L);
+ym_status check_params(const ym_params *p);
+ym_status check_doc_off(const int64_t *o, int64_t n_pairs, const char *what);
+ym_status ensure_table(ym_ctx *c, const ym_params *p, hipStream_t st);
+ym_status plan_chunks(const int64_t *sdo, const int64_t *tdo, int64_t n_pairs, size_t ws_bytes,
+                      std::vector<std::pair<int64_t, int64_t>> &chunks);
+ym_status run_chunk(ym_ctx *c, const ym_lexicon *L, const DevBatch &b, const ym_params *prm, const int64_t *sdo,
+                    const int64_t *tdo, const Chunk &ch, char *ws, const ym_device_out &out, hipStream_t st,
+                    const DebugOut *dbg);
+
+}  // namespace ym
+
+struct ym_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  hipEvent_t staging_done = nullptr;
+  size_t budget = 0;       // serving HBM budget
+  size_t arena_limit = 0;  // workspace cap for host-API calls
+  std::mutex mu;           // one host-API call at a time per context
+  ym::DevBuf table, in, ws, outb;
+  ym::HostBuf staging, host_out;
+  float table_w[4] = {0, 0, 0, 0};
+  bool table_valid = false;
+};

@@ -1,0 +1,249 @@
+"""GPU path (through the C ABI) against the CPU oracle, element by element.
+
+Bars: overlap counts and NW results (H[n][m] bits, paths, emitted pairs)
+bit-exact -- NW is fed the oracle's score matrices; scores within 1e-6; mined
+pair sets identical, apart from explicitly listed admissible ties.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+from . import parity
+
+pytestmark = pytest.mark.gpu
+
+F32 = np.float32
+
+
+@pytest.fixture(scope="module")
+def ym():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1509_08639_amd import ymine
+    return ymine
+
+
+@pytest.fixture(scope="module")
+def ctx(ym):
+    return ym.Context(0)
+
+
+@pytest.fixture(scope="module")
+def O():
+    return oracle.default()
+
+
+def _similarity_check(ym, ctx, O, lex, corpus, w):
+    L = ctx.lexicon(lex.src_ids, lex.off, lex.tgt_ids)
+    S, ms, mt = ym.similarity(ctx, L, corpus, w)
+    OL = O.lexicon(lex.src_ids, lex.off, lex.tgt_ids)
+    base = 0
+    worst = 0.0
+    for p in range(corpus.n_pairs):
+        src, tgt = corpus.pair(p)
+        So, mso, mto = O.similarity(OL, src, tgt, w)
+        k = So.size
+        assert np.array_equal(ms[base:base + k], mso.reshape(-1)), f"m_s differs in pair {p}"
+        assert np.array_equal(mt[base:base + k], mto.reshape(-1)), f"m_t differs in pair {p}"
+        d = np.max(np.abs(S[base:base + k] - So.reshape(-1)), initial=0.0)
+        worst = max(worst, float(d))
+        base += k
+    assert worst <= parity.TOL_S, worst
+    return worst
+
+
+def test_similarity_single_pair(ym, ctx, O):
+    cfg = synth.CONFIGS[0]
+    lex = synth.make_lexicon(cfg)
+    c = synth.generate(cfg, lex)
+    _similarity_check(ym, ctx, O, lex, c, synth.weights(cfg.seed))
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_similarity_ragged_edges(ym, ctx, O, seed):
+    # empty documents and sentences, negative / unknown ids, source sentences
+    # of more than 31 and 62 tokens (extra mask passes), > 128 source
+    # sentences (several work items), > 256 target sentences (several chunks)
+    lex = parity.random_lexicon(seed)
+    c = parity.random_corpus(seed, n_pairs=12, nmax=150, mmax=300, lmax_src=70, lmax_tgt=40)
+    w = np.array([-2.0, 3.0, 2.5, 0.75], np.float32)
+    _similarity_check(ym, ctx, O, lex, c, w)
+
+
+def test_similarity_chunk_boundaries(ym, ctx, O):
+    # target sentences near the 1024-token chunk limit and many short ones
+    lex = parity.random_lexicon(9, vocab=400)
+    r = np.random.default_rng(9)
+    srcs = [[r.integers(0, 400, int(r.integers(1, 40))).astype(np.int32) for _ in range(7)]]
+    tgts = [[r.integers(0, 400, L).astype(np.int32) for L in (1024, 1, 1023, 2, 600, 500, 0, 1024)]]
+    srcs.append([r.integers(0, 400, 5).astype(np.int32) for _ in range(3)])
+    tgts.append([r.integers(0, 400, 3).astype(np.int32) for _ in range(700)])
+    c = synth.from_lists(srcs, tgts)
+    _similarity_check(ym, ctx, O, lex, c, np.array([-1.0, 2.0, 2.0, 0.5], np.float32))
+
+
+def _nw_cases():
+    r = np.random.default_rng(5)
+    mats = []
+    for (n, m) in [(1, 1), (0, 5), (6, 0), (0, 0), (3, 7), (64, 64), (65, 63), (127, 129), (200, 200),
+                   (40, 45), (300, 17), (17, 300), (130, 600), (70, 520), (1000, 1100)]:
+        mats.append(r.random((n, m)).astype(np.float32))
+    # dyadic ties everywhere
+    mats.append((r.integers(0, 3, (90, 77)) / 4.0).astype(np.float32))
+    mats.append(np.full((33, 50), 0.375, np.float32))
+    # denormals, exact threshold values, negative scores
+    S = r.random((20, 25)).astype(np.float32)
+    S[3, 4] = F32(1e-40)
+    S[5, 6] = F32(0.5)
+    S[7, 8] = np.nextafter(F32(0.5), F32(0))
+    S[9, :] = -0.3
+    mats.append(S)
+    return mats
+
+
+@pytest.mark.parametrize("gap", [-0.2, -0.25, 0.0, -1.5])
+def test_nw_fed_oracle_scores(ym, ctx, O, gap):
+    mats = _nw_cases()
+    align, moves, res = ym.nw_align(ctx, mats, gap, 0.5)
+    for k, S in enumerate(mats):
+        h, mv, _ = O.nw(S, gap)
+        assert align[k].tobytes() == h.tobytes(), (k, S.shape, align[k], h)
+        assert moves[k] == mv, (k, S.shape)
+        si, ti, sc = O.emit(S, mv, 0.5)
+        gp, gs = parity.pairs_of(res, k)
+        assert gp == list(zip(si.tolist(), ti.tolist())), k
+        assert gs.tobytes() == sc.tobytes(), k
+
+
+def test_nw_bruteforce_small(ym, ctx, O):
+    from . import pins
+    r = np.random.default_rng(21)
+    mats, gaps = [], []
+    for _ in range(40):
+        n, m = int(r.integers(0, 7)), int(r.integers(0, 7))
+        mats.append(r.random((n, m)).astype(np.float32))
+    align, moves, _ = ym.nw_align(ctx, mats, -0.3, 0.5)
+    for k, S in enumerate(mats):
+        v = pins.folds(S, F32(-0.3), pins.all_paths(*S.shape))
+        assert align[k] == v.max()
+
+
+def test_mine_end_to_end_batch_sample(ym, ctx, O):
+    cfg = synth.CONFIGS[1]
+    lex = synth.make_lexicon(cfg)
+    c = synth.generate(cfg, lex, pair_ids=np.arange(0, 10000, 50))
+    w = synth.weights(cfg.seed)
+    L = ctx.lexicon(lex.src_ids, lex.off, lex.tgt_ids)
+    got = ym.mine(ctx, L, c, w, -0.2, 0.5)
+    OL = O.lexicon(lex.src_ids, lex.off, lex.tgt_ids)
+    want = O.mine(OL, c, w, -0.2, 0.5)
+    S, _, _ = ym.similarity(ctx, L, c, w)
+    ties = parity.compare_mined(O, OL, c, w, F32(-0.2), F32(0.5), got, want, S)
+    assert len(ties) <= 2, ties
+    print("admissible ties:", ties)
+
+
+def test_device_and_per_pair_forms_match(ym, ctx, O):
+    cfg = synth.CONFIGS[1]
+    lex = synth.make_lexicon(cfg)
+    c = synth.generate(cfg, lex, pair_ids=np.arange(300, 420))
+    w = synth.weights(cfg.seed)
+    L = ctx.lexicon(lex.src_ids, lex.off, lex.tgt_ids)
+    a = ym.mine(ctx, L, c, w, -0.2, 0.5)
+    b = ym.mine_per_pair(ctx, L, c, w, -0.2, 0.5)
+    dm = ym.DeviceMiner(ctx, L, c)
+    dm.run(w, -0.2, 0.5)
+    d = dm.result()
+    # a small workspace forces several chunks
+    dm2 = ym.DeviceMiner(ctx, L, c, workspace_bytes=2 << 20)
+    dm2.run(w, -0.2, 0.5)
+    e = dm2.result()
+    for r in (b, d, e):
+        for k in a:
+            assert np.array_equal(a[k], r[k]), k
+
+
+def test_mine_ragged_edges_end_to_end(ym, ctx, O):
+    lex = parity.random_lexicon(4)
+    c = parity.random_corpus(4, n_pairs=30, nmax=90, mmax=90, lmax_src=40, lmax_tgt=35)
+    w = np.array([-1.5, 3.0, 2.0, 0.5], np.float32)
+    L = ctx.lexicon(lex.src_ids, lex.off, lex.tgt_ids)
+    got = ym.mine(ctx, L, c, w, -0.2, 0.5)
+    OL = O.lexicon(lex.src_ids, lex.off, lex.tgt_ids)
+    want = O.mine(OL, c, w, -0.2, 0.5)
+    S, _, _ = ym.similarity(ctx, L, c, w)
+    ties = parity.compare_mined(O, OL, c, w, F32(-0.2), F32(0.5), got, want, S)
+    assert len(ties) <= 1, ties
+
+
+def test_long_pair(ym, ctx, O):
+    cfg = synth.CONFIGS[2]
+    lex = synth.make_lexicon(cfg)
+    c = synth.generate(cfg, lex, pair_ids=np.array([7]))
+    w = synth.weights(cfg.seed)
+    L = ctx.lexicon(lex.src_ids, lex.off, lex.tgt_ids)
+    got = ym.mine(ctx, L, c, w, -0.2, 0.5)
+    OL = O.lexicon(lex.src_ids, lex.off, lex.tgt_ids)
+    want = O.mine(OL, c, w, -0.2, 0.5)
+    S, _, _ = ym.similarity(ctx, L, c, w)
+    ties = parity.compare_mined(O, OL, c, w, F32(-0.2), F32(0.5), got, want, S)
+    assert len(ties) <= 1, ties
+
+
+def test_full_batch_sampled(ym, ctx, O):
+    """The whole 10,000-pair batch in the benchmark's launch shape; the oracle
+    checks a sample of pairs one by one and invariants hold everywhere."""
+    cfg = synth.CONFIGS[1]
+    lex = synth.make_lexicon(cfg)
+    c = synth.generate(cfg, lex)
+    w = synth.weights(cfg.seed)
+    L = ctx.lexicon(lex.src_ids, lex.off, lex.tgt_ids)
+    dm = ym.DeviceMiner(ctx, L, c)
+    dm.run(w, -0.2, 0.5)
+    got = dm.result()
+    n, m = c.nm()
+    cnt = np.diff(got["pair_off"])
+    assert np.all(cnt >= 0) and np.all(cnt <= np.minimum(n, m))
+    assert np.all(got["score"] >= F32(0.5)) and np.all(got["score"] <= 1.0)
+    for p in range(c.n_pairs):
+        a, b = got["pair_off"][p], got["pair_off"][p + 1]
+        assert np.all(np.diff(got["src_idx"][a:b]) > 0) and np.all(np.diff(got["tgt_idx"][a:b]) > 0)
+    sample = np.random.default_rng(0).choice(c.n_pairs, 25, replace=False)
+    sub = c.subset(sample)
+    OL = O.lexicon(lex.src_ids, lex.off, lex.tgt_ids)
+    want = O.mine(OL, sub, w, -0.2, 0.5)
+    for k, p in enumerate(sample):
+        gp, gs = parity.pairs_of(got, int(p))
+        wp, ws = parity.pairs_of(want, k)
+        assert gp == wp and np.max(np.abs(gs - ws), initial=0) <= parity.TOL_S, int(p)
+    # a second run gives the same bits
+    dm.run(w, -0.2, 0.5)
+    again = dm.result()
+    for k in got:
+        assert np.array_equal(got[k], again[k]), k
+
+
+def test_errors(ym, ctx):
+    L = ctx.lexicon(np.array([1], np.int32), np.array([0, 1]), np.array([2], np.int32))
+    c = synth.from_lists([[[1, 2]]], [[[2]]])
+    with pytest.raises(ym.YmError) as e:
+        ym.mine(ctx, L, c, [np.nan, 0, 0, 0], -0.2, 0.5)
+    assert e.value.code == ym.YM_EINVAL
+    bad = synth.from_lists([[[1, 2], [3]]], [[[2]]])
+    bad.src_sent_off = np.array([0, 2, 1], np.int64)  # decreasing sentence offsets
+    with pytest.raises(ym.YmError) as e:
+        ym.mine(ctx, L, bad, [0, 0, 0, 0], -0.2, 0.5)
+    assert e.value.code == ym.YM_EINVAL
+    with pytest.raises(ym.YmError) as e:
+        ctx.lexicon(np.array([-1], np.int32), np.array([0, 1]), np.array([2], np.int32))
+    assert e.value.code == ym.YM_EINVAL
+    long_t = synth.from_lists([[[1]]], [[np.zeros(1025, np.int32)]])
+    with pytest.raises(ym.YmError):
+        ym.mine(ctx, L, long_t, [0, 0, 0, 0], -0.2, 0.5)
+    # empty batch
+    empty = synth.from_lists([], [])
+    r = ym.mine(ctx, L, empty, [0, 0, 0, 0], -0.2, 0.5)
+    assert r["pair_off"].tolist() == [0]
