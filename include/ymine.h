@@ -71,6 +71,8 @@ typedef struct ym_server ym_server;
  * device memory the serving loop may reserve for requests (0: 80% of free
  * memory).  The context owns a device arena reused across calls. */
 ym_status ym_create(int device, size_t hbm_budget_bytes, ym_ctx **out);
+/* Destroy a context.  Stop its servers first; lexicons may be freed before
+ * or after it. */
 void ym_destroy(ym_ctx *ctx);
 
 /* Message of the last failure on this thread; never NULL. */
@@ -208,6 +210,16 @@ ym_status ym_nw_align(ym_ctx *ctx, const float *S, const int32_t *n, const int32
                       float gap, float threshold, float *align_score, char *moves, int32_t *n_moves,
                       ym_result **out);
 
+/* ------------------------------------------------------------ kernel timing */
+
+/* Record HIP events around every kernel the context launches (on the stream
+ * the kernel runs on).  Off by default; costs two event records per launch. */
+ym_status ym_profile_enable(ym_ctx *ctx, int enable);
+/* Summed kernel durations in milliseconds since the last read, by kernel:
+ * ms[0] similarity, ms[1] Needleman-Wunsch, ms[2] scan + compaction;
+ * launches[k] counts the launches.  Waits for the recorded events. */
+ym_status ym_profile_read(ym_ctx *ctx, double ms[3], int64_t launches[3]);
+
 /* -------------------------------------------------- serving (continuous batching) */
 
 typedef struct {
@@ -228,6 +240,13 @@ ym_status ym_submit(ym_server *srv, const ym_batch *one_pair, uint64_t *ticket);
 /* YM_EPENDING until finished; then the result (caller frees) and the ticket
  * is retired.  timeout_us < 0 waits without limit, 0 polls. */
 ym_status ym_poll(ym_server *srv, uint64_t ticket, int64_t timeout_us, ym_result **out);
+/* Next finished ticket in completion order (done, failed or cancelled) and
+ * its completion time in ns of CLOCK_MONOTONIC.  The ticket still has to be
+ * retired with ym_poll.  YM_EPENDING if none finishes within timeout_us
+ * (< 0: wait without limit). */
+ym_status ym_server_next_done(ym_server *srv, int64_t timeout_us, uint64_t *ticket, int64_t *done_ns);
+/* Mark a request cancelled: if not yet admitted it never runs; if running its
+ * result is dropped.  ym_poll then returns YM_ECANCELLED. */
 ym_status ym_cancel(ym_server *srv, uint64_t ticket);
 /* Stop: finishes running steps, cancels what was not admitted, joins. */
 ym_status ym_server_stop(ym_server *srv);

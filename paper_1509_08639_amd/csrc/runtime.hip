@@ -49,12 +49,12 @@ ym_status hip_fail(hipError_t e, const char *what) {
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // ------------------------------------------------------------ device buffer
-ym_status DevBuf::reserve(size_t bytes) {
+ym_status DevBuf::reserve(size_t bytes, bool exact) {
   if (bytes <= cap) return YM_OK;
+  size_t want = exact ? bytes : std::max(bytes, cap * 3 / 2);
   if (ptr) hipFree(ptr);
   ptr = nullptr;
   cap = 0;
-  size_t want = std::max(bytes, cap * 3 / 2);
   hipError_t e = hipMalloc(&ptr, want);
   if (e != hipSuccess) {
     (void)hipGetLastError();
@@ -206,7 +206,8 @@ void Chunk::fill_host(const int64_t *sdo, const int64_t *tdo, char *host) const 
 
 // =================================================================== ABI
 struct ym_lexicon {
-  ym_ctx *ctx = nullptr;
+  ym_ctx *ctx = nullptr;  // not dereferenced on free: the context may be gone already
+  int device = 0;
   int4 *slots = nullptr;
   int32_t *vals = nullptr;
   uint32_t mask = 0;
@@ -236,7 +237,7 @@ ym_status ym_create(int device, size_t hbm_budget_bytes, ym_ctx **out) {
     delete c;
     return hip_fail(e, "hipStreamCreate");
   }
-  if ((e = hipEventCreateWithFlags(&c->staging_done, hipEventDisableTiming)) != hipSuccess) {
+  if ((e = hipEventCreateWithFlags(&c->stage.done, hipEventDisableTiming)) != hipSuccess) {
     hipStreamDestroy(c->stream);
     delete c;
     return hip_fail(e, "hipEventCreate");
@@ -253,13 +254,18 @@ void ym_destroy(ym_ctx *c) {
   if (!c) return;
   hipSetDevice(c->device);
   hipStreamSynchronize(c->stream);
+  for (auto &t : c->ev_pending) {
+    hipEventDestroy(t.a);
+    hipEventDestroy(t.b);
+  }
+  for (auto e : c->ev_free) hipEventDestroy(e);
   c->table.release();
   c->in.release();
   c->ws.release();
   c->outb.release();
-  c->staging.release();
+  c->stage.buf.release();
   c->host_out.release();
-  hipEventDestroy(c->staging_done);
+  hipEventDestroy(c->stage.done);
   hipStreamDestroy(c->stream);
   delete c;
 }
@@ -312,6 +318,7 @@ ym_status ym_lexicon_load(ym_ctx *c, const int32_t *src_ids, const int64_t *off,
   ym_lexicon *L = new (std::nothrow) ym_lexicon();
   if (!L) return fail(YM_ENOMEM, "lexicon allocation");
   L->ctx = c;
+  L->device = c->device;
   L->n_keys = (int64_t)keys.size();
   L->n_pairs = (int64_t)vals.size();
   L->max_fanout = maxf;
@@ -365,13 +372,42 @@ ym_status ym_lexicon_load(ym_ctx *c, const int32_t *src_ids, const int64_t *off,
 
 void ym_lexicon_free(ym_lexicon *L) {
   if (!L) return;
-  if (L->ctx) {
-    hipSetDevice(L->ctx->device);
-    hipStreamSynchronize(L->ctx->stream);
-  }
+  hipSetDevice(L->device);
+  hipDeviceSynchronize();  // no kernel may still read the table
   hipFree(L->slots);
   hipFree(L->vals);
   delete L;
+}
+
+ym_status ym_profile_enable(ym_ctx *c, int enable) {
+  if (!c) return fail(YM_EINVAL, "NULL context");
+  std::lock_guard<std::mutex> lk(c->prof_mu);
+  c->prof = enable != 0;
+  return YM_OK;
+}
+
+ym_status ym_profile_read(ym_ctx *c, double ms[3], int64_t launches[3]) {
+  if (!c || !ms || !launches) return fail(YM_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(c->prof_mu);
+  for (int k = 0; k < 3; k++) {
+    ms[k] = 0.0;
+    launches[k] = 0;
+  }
+  hipSetDevice(c->device);
+  for (auto &t : c->ev_pending) {
+    float x = 0.0f;
+    hipError_t e = hipEventSynchronize(t.b);
+    if (e == hipSuccess) e = hipEventElapsedTime(&x, t.a, t.b);
+    if (e != hipSuccess) return hip_fail(e, "profile read");
+    if (t.kind >= 0 && t.kind < 3) {
+      ms[t.kind] += x;
+      launches[t.kind]++;
+    }
+    c->ev_free.push_back(t.a);
+    c->ev_free.push_back(t.b);
+  }
+  c->ev_pending.clear();
+  return YM_OK;
 }
 
 ym_status ym_lexicon_stats(const ym_lexicon *L, int64_t *n_keys, int64_t *n_pairs, int32_t *max_fanout) {
@@ -452,21 +488,22 @@ ym_status plan_chunks(const int64_t *sdo, const int64_t *tdo, int64_t n_pairs, s
 // Enqueue one chunk: upload its plan, then the four kernels.
 ym_status run_chunk(ym_ctx *c, const ym_lexicon *L, const DevBatch &b, const ym_params *prm, const int64_t *sdo,
                     const int64_t *tdo, const Chunk &ch, char *ws, const ym_device_out &out, hipStream_t st,
-                    const DebugOut *dbg) {
+                    const DebugOut *dbg, Staging *stg) {
   // plan -> pinned staging -> workspace (wait for the previous upload to have left the staging buffer)
-  hipError_t e = hipEventSynchronize(c->staging_done);
+  if (!stg) stg = &c->stage;
+  hipError_t e = hipEventSynchronize(stg->done);
   if (e != hipSuccess) return hip_fail(e, "staging wait");
-  ym_status s = c->staging.reserve(ch.host_bytes);
+  ym_status s = stg->buf.reserve(ch.host_bytes);
   if (s) return s;
-  ch.fill_host(sdo, tdo, (char *)c->staging.ptr);
+  ch.fill_host(sdo, tdo, (char *)stg->buf.ptr);
   const size_t dsz = align256((size_t)ch.np * sizeof(PairDesc));
   const size_t isz = align256((size_t)std::max<int64_t>(ch.n_items, 1) * sizeof(SimItem));
-  const char *hp = (const char *)c->staging.ptr;
+  const char *hp = (const char *)stg->buf.ptr;
   if ((e = hipMemcpyAsync(ws + ch.off_descs, hp, dsz, hipMemcpyHostToDevice, st)) != hipSuccess ||
       (e = hipMemcpyAsync(ws + ch.off_items, hp + dsz, isz, hipMemcpyHostToDevice, st)) != hipSuccess ||
       (e = hipMemcpyAsync(ws + ch.off_moves_off, hp + dsz + isz, align256((size_t)ch.np * 8), hipMemcpyHostToDevice, st)) !=
           hipSuccess ||
-      (e = hipEventRecord(c->staging_done, st)) != hipSuccess)
+      (e = hipEventRecord(stg->done, st)) != hipSuccess)
     return hip_fail(e, "plan upload");
 
   const PairDesc *descs = (const PairDesc *)(ws + ch.off_descs);
@@ -494,7 +531,11 @@ ym_status run_chunk(ym_ctx *c, const ym_lexicon *L, const DevBatch &b, const ym_
     a.ms_out = dbg ? dbg->ms : nullptr;
     a.mt_out = dbg ? dbg->mt : nullptr;
     const int grid = (int)std::min<int64_t>(ch.n_items, (int64_t)1 << 30);
-    if ((e = launch_similarity(a, grid, st)) != hipSuccess) return hip_fail(e, "similarity kernel");
+    {
+      KernelTimer kt(c, 0, st);
+      e = launch_similarity(a, grid, st);
+    }
+    if (e != hipSuccess) return hip_fail(e, "similarity kernel");
     if (dbg && dbg->sim_only) return YM_OK;
   }
   NwArgs n;
@@ -515,11 +556,19 @@ ym_status run_chunk(ym_ctx *c, const ym_lexicon *L, const DevBatch &b, const ym_
   n.moves_off = (const int64_t *)(ws + ch.off_moves_off);
   n.n_moves = dbg ? dbg->n_moves_dev : nullptr;
   if (n.moves) n.moves += dbg->moves_base;
-  if ((e = launch_nw(n, st)) != hipSuccess) return hip_fail(e, "nw kernel");
-  if ((e = launch_scan(n.counts, ch.np, out.pair_off + ch.p0, ch.p0 == 0, st)) != hipSuccess) return hip_fail(e, "scan");
-  if ((e = launch_compact(descs, ch.np, n.counts, out.pair_off + ch.p0, n.slot_src, n.slot_tgt, n.slot_score, out.src_idx,
-                          out.tgt_idx, out.score, st)) != hipSuccess)
-    return hip_fail(e, "compact");
+  {
+    KernelTimer kt(c, 1, st);
+    e = launch_nw(n, st);
+  }
+  if (e != hipSuccess) return hip_fail(e, "nw kernel");
+  {
+    KernelTimer kt(c, 2, st);
+    e = launch_scan(n.counts, ch.np, out.pair_off + ch.p0, ch.p0 == 0, st);
+    if (e == hipSuccess)
+      e = launch_compact(descs, ch.np, n.counts, out.pair_off + ch.p0, n.slot_src, n.slot_tgt, n.slot_score, out.src_idx,
+                         out.tgt_idx, out.score, st);
+  }
+  if (e != hipSuccess) return hip_fail(e, "scan / compact");
   return YM_OK;
 }
 

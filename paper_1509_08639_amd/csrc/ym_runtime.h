@@ -15,7 +15,7 @@ namespace ym {
 struct DevBuf {
   void *ptr = nullptr;
   size_t cap = 0;
-  ym_status reserve(size_t bytes);
+  ym_status reserve(size_t bytes, bool exact = false);
   void release();
 };
 
@@ -62,21 +62,72 @@ ym_status check_doc_off(const int64_t *o, int64_t n_pairs, const char *what);
 ym_status ensure_table(ym_ctx *c, const ym_params *p, hipStream_t st);
 ym_status plan_chunks(const int64_t *sdo, const int64_t *tdo, int64_t n_pairs, size_t ws_bytes,
                       std::vector<std::pair<int64_t, int64_t>> &chunks);
+// Pinned staging buffer for plan uploads and the event that marks its last
+// upload as done (the buffer is rewritten only after that event).
+struct Staging {
+  HostBuf buf;
+  hipEvent_t done = nullptr;
+};
+
 ym_status run_chunk(ym_ctx *c, const ym_lexicon *L, const DevBatch &b, const ym_params *prm, const int64_t *sdo,
                     const int64_t *tdo, const Chunk &ch, char *ws, const ym_device_out &out, hipStream_t st,
-                    const DebugOut *dbg);
+                    const DebugOut *dbg, Staging *stg = nullptr);
 
 }  // namespace ym
 
 struct ym_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
-  hipEvent_t staging_done = nullptr;
+  ym::Staging stage;
   size_t budget = 0;       // serving HBM budget
   size_t arena_limit = 0;  // workspace cap for host-API calls
   std::mutex mu;           // one host-API call at a time per context
   ym::DevBuf table, in, ws, outb;
-  ym::HostBuf staging, host_out;
+  ym::HostBuf host_out;
   float table_w[4] = {0, 0, 0, 0};
   bool table_valid = false;
+  // kernel timing
+  bool prof = false;
+  std::mutex prof_mu;
+  std::vector<hipEvent_t> ev_free;
+  struct Timed {
+    int kind;
+    hipEvent_t a, b;
+  };
+  std::vector<Timed> ev_pending;
+  hipEvent_t ev_get() {
+    if (!ev_free.empty()) {
+      hipEvent_t e = ev_free.back();
+      ev_free.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
 };
+
+namespace ym {
+// Brackets one kernel launch with events when timing is on.
+struct KernelTimer {
+  ym_ctx *c;
+  int kind;
+  hipStream_t st;
+  hipEvent_t a = nullptr, b = nullptr;
+  KernelTimer(ym_ctx *c_, int kind_, hipStream_t st_) : c(c_), kind(kind_), st(st_) {
+    if (c && c->prof) {
+      std::lock_guard<std::mutex> lk(c->prof_mu);
+      a = c->ev_get();
+      b = c->ev_get();
+      if (a && b) hipEventRecord(a, st);
+    }
+  }
+  ~KernelTimer() {
+    if (a && b) {
+      hipEventRecord(b, st);
+      std::lock_guard<std::mutex> lk(c->prof_mu);
+      c->ev_pending.push_back({kind, a, b});
+    }
+  }
+};
+}  // namespace ym

@@ -29,7 +29,8 @@ EXPORTS = [
     "ym_create", "ym_destroy", "ym_last_error", "ym_version", "ym_lexicon_load", "ym_lexicon_free",
     "ym_lexicon_stats", "ym_mine", "ym_result_free", "ym_mine_per_pair", "ym_mine_device_capacity",
     "ym_mine_device_workspace", "ym_mine_device_workspace_min", "ym_mine_device", "ym_similarity",
-    "ym_nw_align", "ym_server_start", "ym_submit", "ym_poll", "ym_cancel", "ym_server_stop",
+    "ym_nw_align", "ym_profile_enable", "ym_profile_read", "ym_server_start", "ym_submit", "ym_poll", "ym_server_next_done", "ym_cancel",
+    "ym_server_stop",
     "ym_server_stats",
 ]
 
@@ -106,9 +107,12 @@ def lib():
     L.ym_similarity.argtypes = [vp, vp, P(Batch), P(Params), P(f32), P(i32), P(i32)]
     L.ym_nw_align.argtypes = [vp, P(f32), P(i32), P(i32), i64, f32, f32, P(f32), C.c_char_p, P(i32),
                               P(P(Result))]
+    L.ym_profile_enable.argtypes = [vp, C.c_int]
+    L.ym_profile_read.argtypes = [vp, P(C.c_double), P(i64)]
     L.ym_server_start.argtypes = [vp, vp, P(Params), P(ServerOpts), P(vp)]
     L.ym_submit.argtypes = [vp, P(Batch), P(u64)]
     L.ym_poll.argtypes = [vp, u64, i64, P(P(Result))]
+    L.ym_server_next_done.argtypes = [vp, i64, P(u64), P(i64)]
     L.ym_cancel.argtypes = [vp, u64]
     L.ym_server_stop.argtypes = [vp]
     L.ym_server_stats.argtypes = [vp, P(i64), P(i64), P(i64)]
@@ -170,11 +174,15 @@ class Context:
     """A device context (ym_create)."""
 
     def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        import weakref
         self.h = vp()
+        self._deps = weakref.WeakSet()  # servers and lexicons, closed before the context
         _check(lib().ym_create(device, hbm_budget_bytes, C.byref(self.h)))
 
     def close(self):
         if self.h:
+            for d in sorted(list(self._deps), key=lambda o: 0 if isinstance(o, Server) else 1):
+                d.close()
             lib().ym_destroy(self.h)
             self.h = vp()
 
@@ -184,6 +192,16 @@ class Context:
         except Exception:
             pass
 
+    def profile(self, enable: bool):
+        _check(lib().ym_profile_enable(self.h, 1 if enable else 0))
+
+    def profile_read(self):
+        """{kernel: (ms summed, launches)} since the last read."""
+        ms = (C.c_double * 3)()
+        n = (i64 * 3)()
+        _check(lib().ym_profile_read(self.h, ms, n))
+        return {k: (ms[i], n[i]) for i, k in enumerate(("similarity", "nw", "compact"))}
+
     def lexicon(self, src_ids, off, tgt_ids) -> "Lexicon":
         return Lexicon(self, src_ids, off, tgt_ids)
 
@@ -192,6 +210,7 @@ class Lexicon:
     def __init__(self, ctx: Context, src_ids, off, tgt_ids):
         self.ctx = ctx
         self.h = vp()
+        ctx._deps.add(self)
         s, o, t = _c(src_ids, np.int32), _c(off, np.int64), _c(tgt_ids, np.int32)
         _check(lib().ym_lexicon_load(ctx.h, _ptr(s, i32), _ptr(o, i64), _ptr(t, i32), int(np.asarray(src_ids).shape[0]),
                                      C.byref(self.h)))
@@ -324,8 +343,8 @@ class Server:
         self.p = params(w, gap, threshold)
         self.opts = ServerOpts(max_pairs_per_step, max_cells_per_step, use_graph)
         self.h = vp()
-        self.keep = {}
         _check(lib().ym_server_start(ctx.h, lex.h, C.byref(self.p), C.byref(self.opts), C.byref(self.h)))
+        ctx._deps.add(self)
 
     def submit(self, corpus_one_pair) -> int:
         hb = _HostBatch(corpus_one_pair)
@@ -334,11 +353,20 @@ class Server:
         return t.value
 
     def poll(self, ticket: int, timeout_us: int = -1):
+        """Result dict, None while pending; raises YmError (YM_ECANCELLED, ...)."""
         rp = P(Result)()
         rc = _check(lib().ym_poll(self.h, ticket, timeout_us, C.byref(rp)))
         if rc == YM_EPENDING:
             return None
         return _result_to_numpy(rp)
+
+    def next_done(self, timeout_us: int = -1):
+        """(ticket, done time in ns of CLOCK_MONOTONIC) or None on timeout."""
+        t, d = u64(), i64()
+        rc = _check(lib().ym_server_next_done(self.h, timeout_us, C.byref(t), C.byref(d)))
+        if rc == YM_EPENDING:
+            return None
+        return t.value, d.value
 
     def cancel(self, ticket: int):
         _check(lib().ym_cancel(self.h, ticket))
@@ -352,3 +380,11 @@ class Server:
         if self.h:
             _check(lib().ym_server_stop(self.h))
             self.h = vp()
+
+    close = stop
+
+    def __del__(self):
+        try:
+            self.stop()
+        except Exception:
+            pass

@@ -1,0 +1,136 @@
+"""Serving loop (continuous batching) on the GPU: every request's result is the
+same alone and in a mix of concurrent requests, equals the batch entry point
+and the oracle, admission respects the HBM budget, and malformed or cancelled
+requests fail on their own."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ym():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1509_08639_amd import ymine
+    return ymine
+
+
+@pytest.fixture(scope="module")
+def setup(ym):
+    cfg = synth.config(3, n_pairs=160, ln_cap=600)
+    lex = synth.make_lexicon(cfg)
+    corpus = synth.generate(cfg, lex)
+    w = synth.weights(cfg.seed)
+    ctx = ym.Context(0)
+    L = ctx.lexicon(lex.src_ids, lex.off, lex.tgt_ids)
+    return cfg, lex, corpus, w, ctx, L
+
+
+def _same(a, b):
+    return all(np.array_equal(a[k], b[k]) for k in ("pair_off", "src_idx", "tgt_idx", "score", "align_score"))
+
+
+def test_alone_equals_in_mix_and_batch(ym, setup):
+    cfg, lex, corpus, w, ctx, L = setup
+    batch = ym.mine(ctx, L, corpus, w, -0.2, 0.5)
+    srv = ym.Server(ctx, L, w, -0.2, 0.5, max_pairs_per_step=32)
+    try:
+        probe = [3, 50, 121]
+        alone = {}
+        for p in probe:
+            t = srv.submit(corpus.subset([p]))
+            alone[p] = srv.poll(t)
+        # the whole corpus from two submitting threads at once
+        tickets = {}
+        lock = threading.Lock()
+
+        def submit(ids):
+            for p in ids:
+                t = srv.submit(corpus.subset([p]))
+                with lock:
+                    tickets[t] = p
+                time.sleep(0.0002)
+        th = [threading.Thread(target=submit, args=(range(k, corpus.n_pairs, 2),)) for k in (0, 1)]
+        for x in th:
+            x.start()
+        for x in th:
+            x.join()
+        mixed = {}
+        for t, p in tickets.items():
+            mixed.setdefault(p, srv.poll(t))
+        stats = srv.stats()
+    finally:
+        srv.stop()
+    assert stats["steps"] > 1 and stats["completed"] >= corpus.n_pairs
+    for p in probe:
+        assert _same(alone[p], mixed[p]), p
+    for p in range(corpus.n_pairs):
+        a, b = batch["pair_off"][p], batch["pair_off"][p + 1]
+        r = mixed[p]
+        assert np.array_equal(r["src_idx"], batch["src_idx"][a:b]) and np.array_equal(r["tgt_idx"], batch["tgt_idx"][a:b])
+        assert np.array_equal(r["score"], batch["score"][a:b]) and r["align_score"][0] == batch["align_score"][p]
+    O = oracle.default()
+    want = O.mine(O.lexicon(lex.src_ids, lex.off, lex.tgt_ids), corpus.subset(probe), w, -0.2, 0.5)
+    for k, p in enumerate(probe):
+        a, b = want["pair_off"][k], want["pair_off"][k + 1]
+        assert np.array_equal(alone[p]["src_idx"], want["src_idx"][a:b])
+
+
+def test_budget_admission(ym, setup):
+    cfg, lex, corpus, w, _, _ = setup
+    ctx = ym.Context(0, hbm_budget_bytes=6 << 20)
+    L = ctx.lexicon(lex.src_ids, lex.off, lex.tgt_ids)
+    n, m = corpus.nm()
+    big = int(np.argmax(n * m))
+    small = [int(p) for p in np.argsort(n * m)[:40]]
+    srv = ym.Server(ctx, L, w, -0.2, 0.5)
+    try:
+        huge = synth.from_lists([[np.arange(5, dtype=np.int32)] * 1500], [[np.arange(5, dtype=np.int32)] * 1500])
+        with pytest.raises(ym.YmError) as e:
+            srv.submit(huge)
+        assert e.value.code == ym.YM_EBUDGET
+        ts = [srv.submit(corpus.subset([p])) for p in small]
+        res = [srv.poll(t) for t in ts]
+        assert all(r is not None for r in res)
+    finally:
+        srv.stop()
+    del big
+
+
+def test_malformed_and_cancelled(ym, setup):
+    cfg, lex, corpus, w, ctx, L = setup
+    srv = ym.Server(ctx, L, w, -0.2, 0.5, max_pairs_per_step=4)
+    try:
+        with pytest.raises(ym.YmError) as e:
+            srv.submit(corpus.subset([1, 2]))  # two pairs in one request
+        assert e.value.code == ym.YM_EINVAL
+        bad = corpus.subset([1])
+        bad.tgt_sent_off = bad.tgt_sent_off.copy()
+        bad.tgt_sent_off[1:] = bad.tgt_sent_off[1:][::-1].copy()
+        with pytest.raises(ym.YmError):
+            srv.submit(bad)
+        ts = [srv.submit(corpus.subset([p])) for p in range(40)]
+        for t in ts[10:30:2]:
+            srv.cancel(t)
+        n_ok = n_cancel = 0
+        for t in ts:
+            try:
+                r = srv.poll(t)
+                n_ok += r is not None
+            except ym.YmError as err:
+                assert err.code == ym.YM_ECANCELLED
+                n_cancel += 1
+        assert n_ok + n_cancel == 40 and n_ok >= 30
+        with pytest.raises(ym.YmError) as e:
+            srv.poll(123456789)
+        assert e.value.code == ym.YM_ENOTFOUND
+    finally:
+        srv.stop()
