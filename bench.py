@@ -69,6 +69,8 @@ def main():
     ap.add_argument("--workload", type=int, default=1, help="workload index (default: the 10k-pair batch)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample (0: skip)")
     ap.add_argument("--per-pair-sample", type=int, default=1000, help="pairs timed in the plain per-pair form")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (calibrates the HBM byte counters) and exit")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -83,6 +85,15 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.copy_probe:
+        n = args.copy_probe << 18  # float32 elements in MIB MiB
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_each_way": n * 4}))
+        return
 
     cfg = synth.CONFIGS[args.workload]
     log(f"[bench] generating workload {cfg.name} ...")

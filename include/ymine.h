@@ -186,9 +186,12 @@ typedef struct {
 
 /* Output capacity: sum over pairs of min(n, m). */
 int64_t ym_mine_device_capacity(const int64_t *src_doc_off, const int64_t *tgt_doc_off, int64_t n_pairs);
-/* Workspace that lets the whole batch run as one chunk, and the minimum. */
-size_t ym_mine_device_workspace(const int64_t *src_doc_off, const int64_t *tgt_doc_off, int64_t n_pairs);
-size_t ym_mine_device_workspace_min(const int64_t *src_doc_off, const int64_t *tgt_doc_off, int64_t n_pairs);
+/* Workspace that lets the whole batch run as one chunk, and the minimum
+ * (both include 16 bytes per source token for the resolved translations). */
+size_t ym_mine_device_workspace(const int64_t *src_doc_off, const int64_t *tgt_doc_off, int64_t n_pairs,
+                                int64_t n_src_tok);
+size_t ym_mine_device_workspace_min(const int64_t *src_doc_off, const int64_t *tgt_doc_off, int64_t n_pairs,
+                                    int64_t n_src_tok);
 
 ym_status ym_mine_device(ym_ctx *ctx, const ym_lexicon *lex, const ym_device_batch *batch,
                          const ym_params *params, void *workspace, size_t workspace_bytes,
@@ -216,9 +219,10 @@ ym_status ym_nw_align(ym_ctx *ctx, const float *S, const int32_t *n, const int32
  * the kernel runs on).  Off by default; costs two event records per launch. */
 ym_status ym_profile_enable(ym_ctx *ctx, int enable);
 /* Summed kernel durations in milliseconds since the last read, by kernel:
- * ms[0] similarity, ms[1] Needleman-Wunsch, ms[2] scan + compaction;
- * launches[k] counts the launches.  Waits for the recorded events. */
-ym_status ym_profile_read(ym_ctx *ctx, double ms[3], int64_t launches[3]);
+ * ms[0] similarity, ms[1] Needleman-Wunsch, ms[2] scan + compaction,
+ * ms[3] source-token translation; launches[k] counts the launches.  Waits
+ * for the recorded events. */
+ym_status ym_profile_read(ym_ctx *ctx, double ms[4], int64_t launches[4]);
 
 /* -------------------------------------------------- serving (continuous batching) */
 

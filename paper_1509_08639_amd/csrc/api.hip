@@ -84,16 +84,16 @@ int64_t capacity_of(const int64_t *sdo, const int64_t *tdo, int64_t n_pairs) {
   return cap;
 }
 
-size_t full_workspace(const int64_t *sdo, const int64_t *tdo, int64_t n_pairs) {
-  size_t b = 16 * 256;
+size_t full_workspace(const int64_t *sdo, const int64_t *tdo, int64_t n_pairs, int64_t n_src_tok) {
+  size_t b = 16 * 256 + trans_bytes(n_src_tok);
   for (int64_t p = 0; p < n_pairs; p++) b += pair_bytes(sdo[p + 1] - sdo[p], tdo[p + 1] - tdo[p]);
   return b;
 }
 
-size_t min_workspace(const int64_t *sdo, const int64_t *tdo, int64_t n_pairs) {
+size_t min_workspace(const int64_t *sdo, const int64_t *tdo, int64_t n_pairs, int64_t n_src_tok) {
   size_t b = 0;
   for (int64_t p = 0; p < n_pairs; p++) b = std::max(b, pair_bytes(sdo[p + 1] - sdo[p], tdo[p + 1] - tdo[p]));
-  return b + 16 * 256;
+  return b + 16 * 256 + trans_bytes(n_src_tok);
 }
 
 // Device output buffers of a host-API call, carved from ctx->outb.
@@ -192,12 +192,14 @@ ym_status mine_host(ym_ctx *c, const ym_lexicon *L, const ym_batch *b, const ym_
   }
 
   std::vector<std::pair<int64_t, int64_t>> chunks;
+  const size_t head = trans_bytes(info.n_src_tok);
   if (mode == Mode::PerPair) {
     for (int64_t p = 0; p < P; p++) chunks.push_back({p, p + 1});
   } else {
-    const size_t full = full_workspace(b->src_doc_off, b->tgt_doc_off, P);
-    const size_t ws = std::max(std::min(full, c->arena_limit), min_workspace(b->src_doc_off, b->tgt_doc_off, P));
-    if ((s = plan_chunks(b->src_doc_off, b->tgt_doc_off, P, ws, chunks))) return s;
+    const size_t full = full_workspace(b->src_doc_off, b->tgt_doc_off, P, info.n_src_tok);
+    const size_t ws = std::max(std::min(full, c->arena_limit + head),
+                               min_workspace(b->src_doc_off, b->tgt_doc_off, P, info.n_src_tok));
+    if ((s = plan_chunks(b->src_doc_off, b->tgt_doc_off, P, ws - head, chunks))) return s;
   }
   size_t need = 0;
   std::vector<Chunk> lay(chunks.size());
@@ -205,7 +207,11 @@ ym_status mine_host(ym_ctx *c, const ym_lexicon *L, const ym_batch *b, const ym_
     lay[k].layout(b->src_doc_off, b->tgt_doc_off, chunks[k].first, chunks[k].second);
     need = std::max(need, lay[k].bytes);
   }
-  if ((s = c->ws.reserve(std::max<size_t>(need, 256)))) {
+  if ((s = c->ws.reserve(head + std::max<size_t>(need, 256)))) {
+    dbgbuf.release();
+    return s;
+  }
+  if ((s = translate_batch(c, L, d, (char *)c->ws.ptr, c->stream))) {
     dbgbuf.release();
     return s;
   }
@@ -214,13 +220,13 @@ ym_status mine_host(ym_ctx *c, const ym_lexicon *L, const ym_batch *b, const ym_
     DebugOut dbg;
     const DebugOut *dp = nullptr;
     if (S_host) {
-      dbg.S = dS + cell_base;
+      dbg.S_rowmajor_out = dS + cell_base;
       dbg.ms = dms + cell_base;
       dbg.mt = dmt + cell_base;
       dbg.sim_only = true;
       dp = &dbg;
     }
-    if ((s = run_chunk(c, L, d, prm, b->src_doc_off, b->tgt_doc_off, lay[k], (char *)c->ws.ptr, o, c->stream, dp))) {
+    if ((s = run_chunk(c, L, d, prm, b->src_doc_off, b->tgt_doc_off, lay[k], (char *)c->ws.ptr + head, o, c->stream, dp))) {
       hipStreamSynchronize(c->stream);
       dbgbuf.release();
       return s;
@@ -273,14 +279,14 @@ int64_t ym_mine_device_capacity(const int64_t *sdo, const int64_t *tdo, int64_t 
   return capacity_of(sdo, tdo, n_pairs);
 }
 
-size_t ym_mine_device_workspace(const int64_t *sdo, const int64_t *tdo, int64_t n_pairs) {
+size_t ym_mine_device_workspace(const int64_t *sdo, const int64_t *tdo, int64_t n_pairs, int64_t n_src_tok) {
   if (!sdo || !tdo || n_pairs < 0) return 0;
-  return full_workspace(sdo, tdo, n_pairs);
+  return full_workspace(sdo, tdo, n_pairs, n_src_tok);
 }
 
-size_t ym_mine_device_workspace_min(const int64_t *sdo, const int64_t *tdo, int64_t n_pairs) {
+size_t ym_mine_device_workspace_min(const int64_t *sdo, const int64_t *tdo, int64_t n_pairs, int64_t n_src_tok) {
   if (!sdo || !tdo || n_pairs < 0) return 0;
-  return min_workspace(sdo, tdo, n_pairs);
+  return min_workspace(sdo, tdo, n_pairs, n_src_tok);
 }
 
 ym_status ym_mine_device(ym_ctx *c, const ym_lexicon *L, const ym_device_batch *b, const ym_params *prm, void *workspace,
@@ -297,8 +303,10 @@ ym_status ym_mine_device(ym_ctx *c, const ym_lexicon *L, const ym_device_batch *
   hipStream_t st = (hipStream_t)stream;
   hipSetDevice(c->device);
   std::lock_guard<std::mutex> lk(c->mu);
+  const size_t head = trans_bytes(b->n_src_tok);
+  if (workspace_bytes < head + 256) return fail(YM_ENOMEM, "workspace smaller than the token translations (%zu bytes)", head);
   std::vector<std::pair<int64_t, int64_t>> chunks;
-  if ((s = plan_chunks(b->src_doc_off, b->tgt_doc_off, b->n_pairs, workspace_bytes, chunks))) return s;
+  if ((s = plan_chunks(b->src_doc_off, b->tgt_doc_off, b->n_pairs, workspace_bytes - head, chunks))) return s;
   if ((s = ensure_table(c, prm, st))) return s;
   DevBatch d;
   d.src_sent_off = b->src_sent_off;
@@ -313,11 +321,13 @@ ym_status ym_mine_device(ym_ctx *c, const ym_lexicon *L, const ym_device_batch *
     hipError_t e = hipMemsetAsync(out->pair_off, 0, 8, st);
     return e ? hip_fail(e, "memset") : YM_OK;
   }
+  if ((s = translate_batch(c, L, d, (char *)workspace, st))) return s;
   for (auto &ck : chunks) {
     Chunk ch;
     ch.layout(b->src_doc_off, b->tgt_doc_off, ck.first, ck.second);
-    if (ch.bytes > workspace_bytes) return fail(YM_ENOMEM, "workspace too small");
-    if ((s = run_chunk(c, L, d, prm, b->src_doc_off, b->tgt_doc_off, ch, (char *)workspace, *out, st, nullptr))) return s;
+    if (ch.bytes > workspace_bytes - head) return fail(YM_ENOMEM, "workspace too small");
+    if ((s = run_chunk(c, L, d, prm, b->src_doc_off, b->tgt_doc_off, ch, (char *)workspace + head, *out, st, nullptr)))
+      return s;
   }
   return YM_OK;
 }
@@ -359,8 +369,8 @@ ym_status ym_nw_align(ym_ctx *c, const float *S, const int32_t *n, const int32_t
     return hip_fail(e, "S upload");
   }
   std::vector<std::pair<int64_t, int64_t>> chunks;
-  const size_t full = full_workspace(sdo.data(), tdo.data(), n_pairs);
-  const size_t wsb = std::max(std::min(full, c->arena_limit), min_workspace(sdo.data(), tdo.data(), n_pairs));
+  const size_t full = full_workspace(sdo.data(), tdo.data(), n_pairs, 0);
+  const size_t wsb = std::max(std::min(full, c->arena_limit), min_workspace(sdo.data(), tdo.data(), n_pairs, 0));
   if ((s = plan_chunks(sdo.data(), tdo.data(), n_pairs, wsb, chunks))) {
     buf.release();
     return s;
@@ -381,11 +391,10 @@ ym_status ym_nw_align(ym_ctx *c, const float *S, const int32_t *n, const int32_t
   prm.threshold = threshold;
   DevBatch d;
   std::memset(&d, 0, sizeof d);
-  int64_t cell_base = 0, mv_base = 0;
+  int64_t cell_base = 0, mv_base = 0;  // no similarity kernel: no token translations
   for (size_t k = 0; k < chunks.size(); k++) {
     DebugOut dbg;
-    dbg.S = dS + cell_base;
-    dbg.S_given = true;
+    dbg.S_rowmajor_in = dS + cell_base;
     dbg.moves_dev = dmv;
     dbg.moves_base = mv_base;
     dbg.n_moves_dev = dnm;

@@ -2,7 +2,7 @@
 //
 //   lex_insert_kernel    builds the HBM-resident lexicon hash (session setup)
 //   score_table_kernel   sentence-pair score for every (a, b, m_s, m_t) with
-//                        a, b < 32, from the current classifier weights
+//                        a, b < 64, from the current classifier weights
 //   sim_kernel           (a) sentence-pair score matrix of each document pair
 //   nw_kernel            (b) Needleman-Wunsch forward pass, traceback and
 //                        threshold filter of each document pair
@@ -37,7 +37,7 @@ __device__ __forceinline__ float ratio_rn(int num, int den) {
   return den == 0 ? 0.0f : __fdiv_rn((float)num, (float)den);
 }
 
-__device__ float score_direct(float w0, float w1, float w2, float w3, int ms, int a, int mt, int b) {
+__device__ __noinline__ float score_direct(float w0, float w1, float w2, float w3, int ms, int a, int mt, int b) {
   const float f1 = ratio_rn(ms, a);
   const float f2 = ratio_rn(mt, b);
   const float f3 = ratio_rn(a < b ? a : b, a < b ? b : a);
@@ -48,10 +48,12 @@ __device__ float score_direct(float w0, float w1, float w2, float w3, int ms, in
   return (float)(1.0 / (1.0 + e));
 }
 
+// table[((a * L + b) * L + ms) * L + mt] = score of (ms, a, mt, b), L = kTabLen
 __global__ __launch_bounds__(256) void score_table_kernel(float w0, float w1, float w2, float w3, float *table) {
   const int idx = blockIdx.x * 256 + threadIdx.x;
-  const int mt = idx & 31, ms = (idx >> 5) & 31, b = (idx >> 10) & 31, a = (idx >> 15) & 31;
-  table[idx] = score_direct(w0, w1, w2, w3, ms, a, mt, b);
+  constexpr int M = kTabLen - 1, B = kLogTabLen;
+  const int mt = idx & M, ms = (idx >> B) & M, b = (idx >> (2 * B)) & M, a = (idx >> (3 * B)) & M;
+  table[idx] = (ms <= a && mt <= b) ? score_direct(w0, w1, w2, w3, ms, a, mt, b) : 0.0f;
 }
 
 // ---------------------------------------------------------------- lexicon
@@ -85,6 +87,25 @@ __device__ __forceinline__ int2 lex_find(const LexDev &L, int32_t x) {
   }
 }
 
+// Translations of every source token of a batch, resolved once per call:
+// up to four target ids inline (-1 padded), or {-2, offset, count, 0} for a
+// key with more than four (read from the value array when used).
+__global__ __launch_bounds__(256) void translate_kernel(const int32_t *tok, int64_t n, LexDev L, int4 *out) {
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (k >= n) return;
+  const int2 oc = lex_find(L, tok[k]);
+  int4 r = make_int4(-1, -1, -1, -1);
+  if (oc.y > 4) {
+    r = make_int4(-2, oc.x, oc.y, 0);
+  } else {
+    if (oc.y > 0) r.x = L.vals[oc.x];
+    if (oc.y > 1) r.y = L.vals[oc.x + 1];
+    if (oc.y > 2) r.z = L.vals[oc.x + 2];
+    if (oc.y > 3) r.w = L.vals[oc.x + 3];
+  }
+  out[k] = r;
+}
+
 // ---------------------------------------------------------- LDS id table
 __device__ __forceinline__ int u_insert(int32_t *ukey, int32_t x) {
   uint32_t h = hash32(x) >> (32 - kLogUcap);
@@ -103,6 +124,24 @@ __device__ __forceinline__ int u_find(const int32_t *ukey, int32_t x) {
     if (k == x) return (int)h;
     if (k == kEmpty) return -1;
     h = (h + 1) & (kUcap - 1);
+  }
+}
+
+// OR `bits` into the word of every translation of one source token that is an
+// id of the staged chunk.
+__device__ __forceinline__ void scatter_token(const int4 t4, uint32_t bits, const int32_t *ukey,
+                                              const uint16_t *ulid, uint32_t *Mw, const int32_t *vals) {
+  if (t4.x == -2) {
+    for (int e = 0; e < t4.z; e++) {
+      const int s = u_find(ukey, vals[t4.y + e]);
+      if (s >= 0) atomicOr(&Mw[ulid[s]], bits);
+    }
+  } else {
+    const int s0 = u_find(ukey, t4.x), s1 = u_find(ukey, t4.y), s2 = u_find(ukey, t4.z), s3 = u_find(ukey, t4.w);
+    if (s0 >= 0) atomicOr(&Mw[ulid[s0]], bits);
+    if (s1 >= 0) atomicOr(&Mw[ulid[s1]], bits);
+    if (s2 >= 0) atomicOr(&Mw[ulid[s2]], bits);
+    if (s3 >= 0) atomicOr(&Mw[ulid[s3]], bits);
   }
 }
 
@@ -131,34 +170,81 @@ __device__ __forceinline__ int block_excl_sum256(int v, int *sh, int *total) {
 
 __device__ __forceinline__ int64_t clamp64(int64_t v, int64_t lo, int64_t hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
+// Score layout.  A pair's n x m score block is stored strip by strip (64 rows
+// per strip, the last one R = n mod 64 rows), and inside a strip by anti-
+// diagonals: cell (l, c) of an R x m strip sits at diag_base(l + c) plus its
+// rank on that diagonal.  The NW sweep below visits exactly one diagonal per
+// step, so each step reads one contiguous run of scores.
+__device__ __forceinline__ int64_t tri(int64_t x) { return x > 0 ? x * (x + 1) / 2 : 0; }
+
+// number of cells of an R x m block on diagonals before t
+__device__ __forceinline__ int64_t diag_base(int64_t t, int64_t R, int64_t m) {
+  return tri(t) - tri(t - R) - tri(t - m) + tri(t - R - m);
+}
+
+// offset of score (i, c) inside its pair's block
+__device__ __forceinline__ int64_t score_pos(int i, int c, int n, int m) {
+  const int s = i >> 6, l = i & 63;
+  const int R = min(64, n - (s << 6));
+  const int t = l + c;
+  return (int64_t)(s << 6) * m + diag_base(t, R, m) + l - max(0, t - m + 1);
+}
+
 // ------------------------------------------------------ (a) similarity
 // One work item = (pair, source sentences [i0, i1)).  Target sentences are
-// taken in chunks of at most kTcap tokens / kJcap sentences.  Each chunk's
-// distinct target ids get dense local ids through an LDS hash, and the chunk's
-// tokens are restaged in LDS as local ids.  A wave then owns one source
-// sentence i at a time: it marks, in an LDS word per local id, which source
-// positions q translate to that id (bit q) and whether the id is in X_i (top
-// bit); every lane takes one target sentence j and walks its tokens:
+// taken in chunks of at most 64 sentences and kTcap tokens.  Each chunk's
+// distinct target ids get dense local ids through an LDS hash, and the
+// chunk's tokens are restaged in LDS as local ids (each sentence padded to a
+// multiple of 4 with id 0).  Lane jj of every wave owns target sentence jj of
+// the chunk and keeps the LDS addresses of its first 32 ids in registers for
+// the whole chunk.  A wave then takes one source sentence i at a time: it
+// marks, in an LDS word per local id, which source positions q translate to
+// that id (bit q) and whether the id is in X_i (top bit, word 0 stays 0), and
+// every lane walks its sentence's words:
 //   m_t = number of tokens whose word has the top bit,
 //   m_s = popcount of the OR of the words' position bits.
-// Sentences longer than 31 tokens take one extra pass per further 31
+// Source sentences longer than 31 tokens take one extra pass per further 31
 // positions (position bits only).
+constexpr int kRegTok = 32;  // target ids per lane held as register addresses
+
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o));
+  return v;
+}
+
+// score_pos in 32-bit arithmetic when the diagonal index stays below 65063
+__device__ __forceinline__ int64_t score_pos_fast(int i, int c, int n, int m) {
+  if (m < 65000) {
+    const int s = i >> 6, l = i & 63;
+    const int R = min(64, n - (s << 6));
+    const int t = l + c;
+    auto tri32 = [](int x) -> uint32_t { return x > 0 ? (uint32_t)x * (uint32_t)(x + 1) / 2u : 0u; };
+    const uint32_t db = tri32(t) - tri32(t - R) - tri32(t - m) + tri32(t - R - m);
+    return (int64_t)(s << 6) * m + (int64_t)db + l - max(0, t - m + 1);
+  }
+  return score_pos(i, c, n, m);
+}
+
 __global__ __launch_bounds__(kSimThreads) void sim_kernel(SimArgs a) {
   __shared__ int32_t ukey[kUcap];
   __shared__ uint16_t ulid[kUcap];
-  __shared__ uint16_t tdoc[kTcap];
-  __shared__ uint16_t toff[kJcap + 1];
+  __shared__ __align__(16) uint16_t tdoc[kTdocCap];
+  __shared__ uint16_t toff[kJcap];        // start of sentence jj in the padded staging
+  __shared__ uint16_t toff_o[kJcap + 1];  // start of sentence jj in the chunk's token range
+  __shared__ uint16_t tlen[kJcap];
   __shared__ __align__(16) uint32_t Mw_all[kSimWaves][kTcap + 4];
   __shared__ int sh_scan[kSimWaves];
   __shared__ int sh_j1;
 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   uint32_t *Mw = Mw_all[wv];
+  const char *Mb = reinterpret_cast<const char *>(Mw);
 
   for (int64_t item = blockIdx.x; item < a.n_items; item += gridDim.x) {
     const SimItem it = a.items[item];
     const PairDesc d = a.descs[it.pair];
-    const int m = d.m;
+    const int n = d.n, m = d.m;
     if (m <= 0 || it.i1 <= it.i0) continue;
     const int64_t *toffs = a.tgt_sent_off + d.tgt_sent0;
     const int64_t *soffs = a.src_sent_off + d.src_sent0;
@@ -182,11 +268,32 @@ __global__ __launch_bounds__(kSimThreads) void sim_kernel(SimArgs a) {
       const int nj = j1 - j0;
       const int64_t tbase = clamp64(toffs[j0], 0, a.n_tgt_tok);
       const int ntok = (int)clamp64(clamp64(toffs[j1], 0, a.n_tgt_tok) - tbase, 0, kTcap);
-      for (int jj = tid; jj <= nj; jj += kSimThreads)
-        toff[jj] = (uint16_t)clamp64(clamp64(toffs[j0 + jj], 0, a.n_tgt_tok) - tbase, 0, ntok);
+      // sentence jj = tid: original local start, length, and start in the padded staging
+      int blen = 0;
+      if (tid < nj) {
+        const int ostart = (int)clamp64(clamp64(toffs[j0 + tid], 0, a.n_tgt_tok) - tbase, 0, ntok);
+        const int oend = (int)clamp64(clamp64(toffs[j0 + tid + 1], 0, a.n_tgt_tok) - tbase, ostart, ntok);
+        blen = oend - ostart;
+        toff_o[tid] = (uint16_t)ostart;
+        tlen[tid] = (uint16_t)blen;
+      }
+      int npad;
+      const int pstart = block_excl_sum256((blen + 3) & ~3, sh_scan, &npad);
+      if (tid < nj) toff[tid] = (uint16_t)pstart;
+      if (tid == 0) toff_o[nj] = (uint16_t)ntok;
+      for (int q = tid; q < npad; q += kSimThreads) tdoc[q] = 0xFFFF;
+      __syncthreads();
       for (int p = tid; p < ntok; p += kSimThreads) {
+        int lo = 0, hi = nj - 1;  // sentence holding token p: last start <= p
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (toff_o[mid] <= p)
+            lo = mid;
+          else
+            hi = mid - 1;
+        }
         const int32_t x = a.tgt_tok[tbase + p];
-        tdoc[p] = x < 0 ? (uint16_t)0xFFFF : (uint16_t)u_insert(ukey, x);
+        tdoc[toff[lo] + (p - toff_o[lo])] = x < 0 ? (uint16_t)0xFFFF : (uint16_t)u_insert(ukey, x);
       }
       __syncthreads();
       // dense local ids 1..nlid-1 in slot order (0 = "no such id", its word stays 0)
@@ -203,72 +310,85 @@ __global__ __launch_bounds__(kSimThreads) void sim_kernel(SimArgs a) {
       }
       const int nlid = total + 1;
       __syncthreads();
-      for (int p = tid; p < ntok; p += kSimThreads) {
-        const uint16_t s = tdoc[p];
-        tdoc[p] = s == 0xFFFF ? (uint16_t)0 : ulid[s];
+      for (int q = tid; q < npad; q += kSimThreads) {
+        const uint16_t s = tdoc[q];
+        tdoc[q] = s == 0xFFFF ? (uint16_t)0 : ulid[s];
       }
       __syncthreads();
 
+      // this lane's target sentence and its word addresses
+      const bool jok = lane < nj;
+      const int bl = jok ? tlen[lane] : 0;
+      const uint16_t *tp = tdoc + (jok ? toff[lane] : 0);
+      uint32_t ad[kRegTok];
+#pragma unroll
+      for (int k = 0; k < kRegTok; k++) ad[k] = k < bl ? (uint32_t)tp[k] << 2 : 0u;
+      const int maxb = wave_max(bl);
+      const int ng = (min(maxb, kRegTok) + 3) >> 2;
       const int nq4 = (nlid + 3) >> 2;
+
+      // translations of the wave's next source sentence (positions < 64) are
+      // fetched one sentence ahead
+      auto fetch = [&](int ii) -> int4 {
+        if (ii >= it.i1) return make_int4(-1, -1, -1, -1);
+        const int64_t b0 = clamp64(soffs[ii], 0, a.n_src_tok);
+        const int64_t b1 = clamp64(soffs[ii + 1], b0, a.n_src_tok);
+        return lane < b1 - b0 ? a.trans[b0 + lane] : make_int4(-1, -1, -1, -1);
+      };
+      int4 pre = fetch(it.i0 + wv);
       for (int i = it.i0 + wv; i < it.i1; i += kSimWaves) {
         const int64_t sb = clamp64(soffs[i], 0, a.n_src_tok);
         const int64_t se = clamp64(soffs[i + 1], sb, a.n_src_tok);
         const int ai = (int)min<int64_t>(se - sb, 0x7fffffff);
         const int npass = ai <= kPosBits ? 1 : (ai + kPosBits - 1) / kPosBits;
-        uint32_t ms_acc[kJpass], mt_acc[kJpass];
-#pragma unroll
-        for (int tp = 0; tp < kJpass; tp++) ms_acc[tp] = mt_acc[tp] = 0;
-
+        const int4 cur = pre;
+        pre = fetch(i + kSimWaves);
+        uint32_t ms_acc = 0, mt_acc = 0;
         for (int c = 0; c < npass; c++) {
           for (int k = lane; k < nq4; k += 64) reinterpret_cast<uint4 *>(Mw)[k] = make_uint4(0, 0, 0, 0);
           wave_sync();
           const int qlo = c == 0 ? 0 : kPosBits * c;
           const int qhi = c == 0 ? ai : min(ai, kPosBits * c + kPosBits);
           for (int q = qlo + lane; q < qhi; q += 64) {
-            const int2 oc = lex_find(a.lex, a.src_tok[sb + q]);
+            const int4 t4 = (c == 0 && q < 64) ? cur : a.trans[sb + q];
             const int rel = q - kPosBits * c;
             const uint32_t bits = (c == 0 ? kHitBit : 0u) | (rel >= 0 && rel < kPosBits ? (1u << rel) : 0u);
-            for (int e = 0; e < oc.y; e++) {
-              const int s = u_find(ukey, a.lex.vals[oc.x + e]);
-              if (s >= 0) atomicOr(&Mw[ulid[s]], bits);
-            }
+            scatter_token(t4, bits, ukey, ulid, Mw, a.lex.vals);
           }
           wave_sync();
+          uint32_t acc = 0, mt = 0;
 #pragma unroll
-          for (int tp = 0; tp < kJpass; tp++) {
-            if (tp * 64 < nj) {
-              const int jj = tp * 64 + lane;
-              if (jj < nj) {
-                const int p0 = toff[jj], p1 = toff[jj + 1];
-                uint32_t acc = 0, mt = 0;
-                for (int p = p0; p < p1; p++) {
-                  const uint32_t mk = Mw[tdoc[p]];
-                  mt += mk >> 31;
-                  acc |= mk;
-                }
-                ms_acc[tp] += __popc(acc & ~kHitBit);
-                if (c == 0) mt_acc[tp] = mt;
-              }
+          for (int g = 0; g < kRegTok / 4; g++) {
+            if (g < ng) {
+              const uint32_t w0 = *reinterpret_cast<const uint32_t *>(Mb + ad[4 * g]);
+              const uint32_t w1 = *reinterpret_cast<const uint32_t *>(Mb + ad[4 * g + 1]);
+              const uint32_t w2 = *reinterpret_cast<const uint32_t *>(Mb + ad[4 * g + 2]);
+              const uint32_t w3 = *reinterpret_cast<const uint32_t *>(Mb + ad[4 * g + 3]);
+              mt += ((w0 >> 31) + (w1 >> 31)) + ((w2 >> 31) + (w3 >> 31));
+              acc |= (w0 | w1) | (w2 | w3);
             }
           }
+          if (maxb > kRegTok) {  // sentences beyond 32 tokens: the rest straight from LDS
+            for (int k = kRegTok; k < bl; k++) {
+              const uint32_t w = Mw[tp[k]];
+              mt += w >> 31;
+              acc |= w;
+            }
+          }
+          ms_acc += __popc(acc & ~kHitBit);
+          if (c == 0) mt_acc = mt;
           wave_sync();
         }
-        float *Srow = a.S + d.s_off + (int64_t)i * m + j0;
-#pragma unroll
-        for (int tp = 0; tp < kJpass; tp++) {
-          const int jj = tp * 64 + lane;
-          if (tp * 64 < nj && jj < nj) {
-            const int bj = toff[jj + 1] - toff[jj];
-            const int ms = (int)ms_acc[tp], mt = (int)mt_acc[tp];
-            const float sv = (ai < kTabLen && bj < kTabLen)
-                                 ? a.table[((ai * kTabLen + bj) * kTabLen + ms) * kTabLen + mt]
-                                 : score_direct(a.w0, a.w1, a.w2, a.w3, ms, ai, mt, bj);
-            Srow[jj] = sv;
-            if (a.ms_out) {
-              const int64_t cell = d.s_off + (int64_t)i * m + j0 + jj;
-              a.ms_out[cell] = ms;
-              a.mt_out[cell] = mt;
-            }
+        if (jok) {
+          const int ms = (int)ms_acc, mt = (int)mt_acc;
+          const float sv = (ai < kTabLen && bl < kTabLen)
+                               ? a.table[((ai * kTabLen + bl) * kTabLen + ms) * kTabLen + mt]
+                               : score_direct(a.w0, a.w1, a.w2, a.w3, ms, ai, mt, bl);
+          a.S[d.s_off + score_pos_fast(i, j0 + lane, n, m)] = sv;
+          if (a.ms_out) {
+            const int64_t cell = d.s_off + (int64_t)i * m + j0 + lane;
+            a.ms_out[cell] = ms;
+            a.mt_out[cell] = mt;
           }
         }
       }
@@ -278,20 +398,103 @@ __global__ __launch_bounds__(kSimThreads) void sim_kernel(SimArgs a) {
   }
 }
 
-// ------------------------------------------------------------- (b) NW
+// Row-major <-> strip-diagonal copies of whole score blocks (parity entries).
+__global__ __launch_bounds__(256) void relayout_kernel(const PairDesc *descs, int64_t n_pairs, const float *src,
+                                                       float *dst, int to_diag) {
+  const int64_t p = blockIdx.y;
+  if (p >= n_pairs) return;
+  const PairDesc d = descs[p];
+  const int64_t cells = (int64_t)d.n * d.m;
+  for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < cells; k += (int64_t)gridDim.x * 256) {
+    const int i = (int)(k / d.m), c = (int)(k % d.m);
+    const int64_t q = score_pos(i, c, d.n, d.m);
+    if (to_diag)
+      dst[d.s_off + q] = src[d.s_off + k];
+    else
+      dst[d.s_off + k] = src[d.s_off + q];
+  }
+}
+
 // One wave per document pair.  Rows are taken in strips of 64 (lane l owns
 // DP row 64*s + l + 1); the strip sweeps the columns along anti-diagonals:
 // at step t lane l computes column j = t - l.  The value from the row above
 // arrives from lane l-1 through a one-lane DPP shift; lane 0 reads it from the
 // previous strip's bottom row (or the top boundary, built by repeated
-// addition).  Direction codes (D=0, U=1, L=2) are packed 16 per word, row-
-// major, in LDS when the pair fits, else in global scratch.  Lane 0 then walks
-// the path back from (n, m), writing the D cells backwards into the pair's
-// output slots; the wave reads their scores, keeps those >= tau and compacts
-// them in path order to the front of the slots.
+// addition).  Scores are prefetched 16 steps ahead into registers.
+// Direction codes (D=0, U=1, L=2) are packed 16 per word, row-major, in LDS
+// when the pair fits, else in global scratch.  Lane 0 then walks the path
+// back from (n, m), writing the D cells backwards into the pair's output
+// slots; the wave reads their scores, keeps those >= tau and compacts them in
+// path order to the front of the slots.
 __device__ __forceinline__ float shift_up_one_lane(float v) {
   // wave_shr:1 -- lane l receives lane l-1's value (lane 0 keeps its own)
   return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x138, 0xF, 0xF, false));
+}
+
+constexpr int kNwUnroll = 16;
+
+struct NwLane {
+  float h, upv, topv;
+  uint32_t dw;
+};
+
+// Scores of the next 16 steps for this lane.  Step t reads diagonal t-1 of
+// the strip; the cursor (diagonal d, its offset `base` in the strip block)
+// advances by one diagonal per step.  Lane 0 of strips after the first also
+// fetches the previous strip's bottom row value H[64s][t] for each step.
+__device__ __forceinline__ void nw_prefetch(float (&buf)[kNwUnroll], float (&rb)[kNwUnroll], const float *blk,
+                                            const float *rowbuf, bool use_row, int &d, int &base, int lane, int R,
+                                            int m) {
+#pragma unroll
+  for (int k = 0; k < kNwUnroll; k++) {
+    const int c = d - lane;
+    const int lo = max(0, d - m + 1);
+    const int hi = min(R - 1, d);
+    const bool ok = lane < R && c >= 0 && c < m;
+    buf[k] = ok ? blk[base + lane - lo] : 0.0f;
+    const int t = d + 1;
+    rb[k] = (use_row && lane == 0 && t <= m) ? rowbuf[t] : 0.0f;
+    base += max(0, hi - lo + 1);
+    d++;
+  }
+}
+
+// 16 steps of the strip sweep, written without divergent branches except
+// for the direction-word flush and the bottom-row hand-off (a few lanes).
+__device__ __forceinline__ void nw_steps(const float (&buf)[kNwUnroll], const float (&rb)[kNwUnroll], int t0,
+                                         int tend, NwLane &L, int lane, int s, int i, bool rowok, int lastlane,
+                                         int nstrips, int m, int W, float g, uint32_t *dirs, float *rowbuf) {
+#pragma unroll
+  for (int k = 0; k < kNwUnroll; k++) {
+    const int t = t0 + k;
+    if (t > tend) break;
+    const float from_left_lane = shift_up_one_lane(L.h);
+    L.topv = t == 0 ? 0.0f : __fadd_rn(L.topv, g);  // H[0][t], top boundary
+    const float up0 = s == 0 ? L.topv : rb[k];
+    const float up = lane == 0 ? up0 : from_left_lane;
+    const int j = t - lane;
+    const bool act = rowok && j >= 0 && j <= m;
+    const float dd = __fadd_rn(L.upv, buf[k]);
+    const float uu = __fadd_rn(up, g);
+    const float ll = __fadd_rn(L.h, g);
+    const bool u_wins = uu > dd;
+    float best = u_wins ? uu : dd;
+    uint32_t code = u_wins ? 1u : 0u;
+    const bool l_wins = ll > best;
+    best = l_wins ? ll : best;
+    code = l_wins ? 2u : code;
+    const float hn = j == 0 ? uu : best;  // column 0: H[i][0] = H[i-1][0] + g
+    const int jc = j - 1;
+    const bool cell = act && j >= 1;
+    L.dw |= cell ? code << (2 * (jc & 15)) : 0u;
+    if (cell && ((jc & 15) == 15 || j == m)) {
+      dirs[(int64_t)(i - 1) * W + (jc >> 4)] = L.dw;
+      L.dw = 0;
+    }
+    if (act && lane == lastlane && s + 1 < nstrips) rowbuf[j] = hn;
+    L.upv = act ? up : L.upv;
+    L.h = act ? hn : L.h;
+  }
 }
 
 template <bool kLds>
@@ -309,57 +512,22 @@ __device__ __forceinline__ void nw_pair(const NwArgs &a, const PairDesc &d, int6
     for (int s = 0; s < nstrips; s++) {
       const int i = s * 64 + lane + 1;
       const bool rowok = i <= n;
-      const int lastlane = min(63, n - s * 64 - 1);
-      const float *Srow = S + (int64_t)(rowok ? i - 1 : 0) * m;
-      float h = 0.0f, upv = 0.0f, topv = 0.0f;
-      float snext = rowok ? Srow[0] : 0.0f;
-      uint32_t dw = 0;
+      const int R = min(64, n - s * 64);
+      const int lastlane = R - 1;
+      const float *blk = S + (int64_t)(s * 64) * m;
+      NwLane L{0.0f, 0.0f, 0.0f, 0u};
       const int tend = m + lastlane;
-      for (int t = 0; t <= tend; t++) {
-        float up = shift_up_one_lane(h);
-        if (lane == 0) {
-          if (s == 0) {
-            topv = t == 0 ? 0.0f : __fadd_rn(topv, g);
-            up = topv;
-          } else if (t <= m) {
-            up = rowbuf[t];
-          }
-        }
-        const int j = t - lane;
-        if (rowok && j >= 0 && j <= m) {
-          float hn;
-          if (j == 0) {
-            hn = __fadd_rn(up, g);
-          } else {
-            const float sv = snext;
-            if (j < m) snext = Srow[j];
-            const float dd = __fadd_rn(upv, sv);
-            const float uu = __fadd_rn(up, g);
-            const float ll = __fadd_rn(h, g);
-            float best = dd;
-            uint32_t code = 0;
-            if (uu > best) {
-              best = uu;
-              code = 1;
-            }
-            if (ll > best) {
-              best = ll;
-              code = 2;
-            }
-            hn = best;
-            const int jc = j - 1;
-            dw |= code << (2 * (jc & 15));
-            if ((jc & 15) == 15 || j == m) {
-              dirs[(int64_t)(i - 1) * W + (jc >> 4)] = dw;
-              dw = 0;
-            }
-          }
-          upv = up;
-          h = hn;
-          if (lane == lastlane && s + 1 < nstrips) rowbuf[j] = hn;
-        }
+      float bufA[kNwUnroll], bufB[kNwUnroll], rbA[kNwUnroll], rbB[kNwUnroll];
+      int cd = -1, cbase = 0;  // prefetch cursor: step t reads diagonal t-1
+      const bool use_row = s > 0;
+      nw_prefetch(bufA, rbA, blk, rowbuf, use_row, cd, cbase, lane, R, m);
+      for (int t0 = 0; t0 <= tend; t0 += 2 * kNwUnroll) {
+        nw_prefetch(bufB, rbB, blk, rowbuf, use_row, cd, cbase, lane, R, m);
+        nw_steps(bufA, rbA, t0, tend, L, lane, s, i, rowok, lastlane, nstrips, m, W, g, dirs, rowbuf);
+        nw_prefetch(bufA, rbA, blk, rowbuf, use_row, cd, cbase, lane, R, m);
+        nw_steps(bufB, rbB, t0 + kNwUnroll, tend, L, lane, s, i, rowok, lastlane, nstrips, m, W, g, dirs, rowbuf);
       }
-      if (s == nstrips - 1) hnm = __shfl(h, lastlane);
+      if (s == nstrips - 1) hnm = __shfl(L.h, lastlane);
       if (kLds)
         wave_sync();
       else
@@ -445,7 +613,7 @@ __device__ __forceinline__ void nw_pair(const NwArgs &a, const PairDesc &d, int6
       const int64_t r = slot_end - K + k;
       si = a.slot_src[r];
       ti = a.slot_tgt[r];
-      sv = S[(int64_t)si * m + ti];
+      sv = S[score_pos(si, ti, n, m)];
       keep = sv >= a.tau;
     }
     const uint64_t bal = __ballot(keep);
@@ -547,6 +715,12 @@ hipError_t launch_lex_insert(const int32_t *keys, const int32_t *cnts, const int
   return hipGetLastError();
 }
 
+hipError_t launch_translate(const int32_t *tok, int64_t n, const LexDev &L, int4 *out, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(translate_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, tok, n, L, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_score_table(float w0, float w1, float w2, float w3, float *table, hipStream_t st) {
   constexpr int N = kTabLen * kTabLen * kTabLen * kTabLen;
   hipLaunchKernelGGL(score_table_kernel, dim3(N / 256), dim3(256), 0, st, w0, w1, w2, w3, table);
@@ -576,6 +750,13 @@ hipError_t launch_compact(const PairDesc *descs, int64_t n_pairs, const int32_t 
   if (n_pairs <= 0) return hipSuccess;
   hipLaunchKernelGGL(compact_kernel, dim3((unsigned)n_pairs), dim3(64), 0, st, descs, n_pairs, counts, po, slot_src,
                      slot_tgt, slot_score, out_src, out_tgt, out_score);
+  return hipGetLastError();
+}
+
+hipError_t launch_relayout(const PairDesc *descs, int64_t n_pairs, const float *src, float *dst, int to_diag,
+                           hipStream_t st) {
+  if (n_pairs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(relayout_kernel, dim3(64, (unsigned)n_pairs), dim3(256), 0, st, descs, n_pairs, src, dst, to_diag);
   return hipGetLastError();
 }
 

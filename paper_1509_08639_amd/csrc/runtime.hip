@@ -386,10 +386,10 @@ ym_status ym_profile_enable(ym_ctx *c, int enable) {
   return YM_OK;
 }
 
-ym_status ym_profile_read(ym_ctx *c, double ms[3], int64_t launches[3]) {
+ym_status ym_profile_read(ym_ctx *c, double ms[4], int64_t launches[4]) {
   if (!c || !ms || !launches) return fail(YM_EINVAL, "NULL argument");
   std::lock_guard<std::mutex> lk(c->prof_mu);
-  for (int k = 0; k < 3; k++) {
+  for (int k = 0; k < 4; k++) {
     ms[k] = 0.0;
     launches[k] = 0;
   }
@@ -399,7 +399,7 @@ ym_status ym_profile_read(ym_ctx *c, double ms[3], int64_t launches[3]) {
     hipError_t e = hipEventSynchronize(t.b);
     if (e == hipSuccess) e = hipEventElapsedTime(&x, t.a, t.b);
     if (e != hipSuccess) return hip_fail(e, "profile read");
-    if (t.kind >= 0 && t.kind < 3) {
+    if (t.kind >= 0 && t.kind < 4) {
       ms[t.kind] += x;
       launches[t.kind]++;
     }
@@ -451,6 +451,16 @@ ym_status ensure_table(ym_ctx *c, const ym_params *p, hipStream_t st) {
   std::memcpy(c->table_w, p->w, sizeof c->table_w);
   c->table_valid = true;
   return YM_OK;
+}
+
+ym_status translate_batch(ym_ctx *c, const ym_lexicon *L, DevBatch &b, char *head, hipStream_t st) {
+  b.trans = (const int4 *)head;
+  hipError_t e;
+  {
+    KernelTimer kt(c, 3, st);
+    e = launch_translate(b.src_tok, b.n_src_tok, lex_dev(L), (int4 *)head, st);
+  }
+  return e == hipSuccess ? YM_OK : hip_fail(e, "translate kernel");
 }
 
 // Validate a host pair table: offsets start at 0 and never decrease.
@@ -507,8 +517,10 @@ ym_status run_chunk(ym_ctx *c, const ym_lexicon *L, const DevBatch &b, const ym_
     return hip_fail(e, "plan upload");
 
   const PairDesc *descs = (const PairDesc *)(ws + ch.off_descs);
-  float *S = dbg && dbg->S ? dbg->S : (float *)(ws + ch.off_S);
-  if (!(dbg && dbg->S_given)) {
+  float *S = (float *)(ws + ch.off_S);  // strip-diagonal layout
+  if (dbg && dbg->S_rowmajor_in) {
+    if ((e = launch_relayout(descs, ch.np, dbg->S_rowmajor_in, S, 1, st)) != hipSuccess) return hip_fail(e, "relayout");
+  } else {
     SimArgs a;
     a.items = (const SimItem *)(ws + ch.off_items);
     a.n_items = ch.n_items;
@@ -522,6 +534,7 @@ ym_status run_chunk(ym_ctx *c, const ym_lexicon *L, const DevBatch &b, const ym_
     a.n_src_tok = b.n_src_tok;
     a.n_tgt_tok = b.n_tgt_tok;
     a.lex = lex_dev(L);
+    a.trans = b.trans;
     a.w0 = prm->w[0];
     a.w1 = prm->w[1];
     a.w2 = prm->w[2];
@@ -536,6 +549,9 @@ ym_status run_chunk(ym_ctx *c, const ym_lexicon *L, const DevBatch &b, const ym_
       e = launch_similarity(a, grid, st);
     }
     if (e != hipSuccess) return hip_fail(e, "similarity kernel");
+    if (dbg && dbg->S_rowmajor_out &&
+        (e = launch_relayout(descs, ch.np, S, dbg->S_rowmajor_out, 0, st)) != hipSuccess)
+      return hip_fail(e, "relayout");
     if (dbg && dbg->sim_only) return YM_OK;
   }
   NwArgs n;

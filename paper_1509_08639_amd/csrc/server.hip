@@ -57,7 +57,7 @@ struct Request {
 
 // Device bytes one request adds to a step: its inputs, workspace share and outputs.
 size_t request_bytes(int64_t n, int64_t m, int64_t ntok_s, int64_t ntok_t) {
-  return a256((size_t)(n + m + 2) * 8) + a256((size_t)(ntok_s + ntok_t) * 4 + 8) + pair_bytes(n, m) +
+  return a256((size_t)(n + m + 2) * 8) + a256((size_t)(ntok_s + ntok_t) * 4 + 8) + trans_bytes(ntok_s) + pair_bytes(n, m) +
          a256((size_t)std::min(n, m) * 12 + 16) + 1024;
 }
 
@@ -123,7 +123,8 @@ ym_status launch_step(ym_server *S, Slot &sl) {
   ym_status s;
   if ((s = sl.hin.reserve(in_bytes))) return s;
   if ((s = sl.hout.reserve(out_bytes))) return s;
-  if ((s = sl.dev.reserve(in_bytes + a256(ch.bytes) + out_bytes, true))) return s;
+  const size_t head = trans_bytes(nts);
+  if ((s = sl.dev.reserve(in_bytes + head + a256(ch.bytes) + out_bytes, true))) return s;
 
   // pack inputs (global sentence offsets)
   char *h = (char *)sl.hin.ptr;
@@ -153,9 +154,10 @@ ym_status launch_step(ym_server *S, Slot &sl) {
   b.n_tgt_sent = NT;
   b.n_src_tok = nts;
   b.n_tgt_tok = ntt;
-  char *ws = d + in_bytes;
+  if ((s = translate_batch(S->ctx, S->lex, b, d + in_bytes, sl.stream))) return s;
+  char *ws = d + in_bytes + head;
   char *ob = ws + a256(ch.bytes);
-  sl.off_out = in_bytes + a256(ch.bytes);
+  sl.off_out = in_bytes + head + a256(ch.bytes);
   ym_device_out o;
   o.pair_off = (int64_t *)ob;
   o.align_score = (float *)(ob + o1);

@@ -16,10 +16,12 @@ constexpr int kSimWaves = kSimThreads / 64;
 constexpr int kTcap = 1024;             // max target tokens staged per chunk (and per sentence)
 constexpr int kUcap = 2 * kTcap;        // LDS hash slots for the chunk's distinct target ids
 constexpr int kLogUcap = 11;
-constexpr int kJcap = 256;              // max target sentences per chunk
-constexpr int kJpass = kJcap / 64;      // target-sentence passes of one wave
+constexpr int kJcap = 64;               // max target sentences per chunk (one per lane)
+constexpr int kTdocCap = kTcap + 3 * kJcap;  // staged ids, each sentence padded to a multiple of 4
+static_assert(kJcap <= kSimThreads && kJcap == 64, "one lane per target sentence of a chunk");
 constexpr int kItemRows = 128;          // source sentences per work item
-constexpr int kTabLen = 32;             // score table covers sentence lengths < 32
+constexpr int kTabLen = 64;             // score table covers sentence lengths < 64
+constexpr int kLogTabLen = 6;
 
 // NW kernel staging.
 constexpr int kDirLds = 2688;           // direction words held in LDS (covers 200 x 200)
@@ -65,6 +67,7 @@ struct SimArgs {
   const int32_t *tgt_tok;
   int64_t n_src_sent, n_tgt_sent, n_src_tok, n_tgt_tok;
   LexDev lex;
+  const int4 *trans;  // translations of every source token (translate_kernel)
   float w0, w1, w2, w3;
   const float *table;  // kTabLen^4 scores for short sentences
   float *S;
@@ -92,6 +95,7 @@ struct NwArgs {
 // Launch wrappers (kernels.hip).
 hipError_t launch_lex_insert(const int32_t *keys, const int32_t *cnts, const int64_t *offs, int64_t n, int4 *slots,
                              uint32_t mask, int shift, hipStream_t st);
+hipError_t launch_translate(const int32_t *tok, int64_t n, const LexDev &L, int4 *out, hipStream_t st);
 hipError_t launch_score_table(float w0, float w1, float w2, float w3, float *table, hipStream_t st);
 hipError_t launch_similarity(const SimArgs &a, int grid, hipStream_t st);
 hipError_t launch_nw(const NwArgs &a, hipStream_t st);
@@ -99,6 +103,8 @@ hipError_t launch_scan(const int32_t *counts, int64_t n, int64_t *pair_off_at_p0
 hipError_t launch_compact(const PairDesc *descs, int64_t n_pairs, const int32_t *counts, const int64_t *pair_off_at_p0,
                           const int32_t *slot_src, const int32_t *slot_tgt, const float *slot_score, int32_t *out_src,
                           int32_t *out_tgt, float *out_score, hipStream_t st);
+hipError_t launch_relayout(const PairDesc *descs, int64_t n_pairs, const float *src, float *dst, int to_diag,
+                           hipStream_t st);
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st);
 
 }  // namespace ym

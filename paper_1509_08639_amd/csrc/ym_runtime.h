@@ -31,13 +31,17 @@ struct DevBatch {
   const int64_t *src_sent_off, *tgt_sent_off;
   const int32_t *src_tok, *tgt_tok;
   int64_t n_src_sent, n_tgt_sent, n_src_tok, n_tgt_tok;
+  const int4 *trans;  // translations of every source token (workspace head)
 };
+
+// Workspace head that holds the source-token translations of a batch.
+inline size_t trans_bytes(int64_t n_src_tok) { return ((size_t)(n_src_tok > 0 ? n_src_tok : 0) * 16 + 255) & ~size_t(255); }
 
 // Optional debug outputs of a chunk run.
 struct DebugOut {
-  float *S = nullptr;        // if set: score matrices go here (device, chunk-local layout)
-  bool S_given = false;      // S already holds the scores: skip the similarity kernel
-  bool sim_only = false;     // stop after the similarity kernel
+  float *S_rowmajor_out = nullptr;       // if set: the chunk's scores, row-major, go here (device)
+  const float *S_rowmajor_in = nullptr;  // if set: use these row-major scores, skip the similarity kernel
+  bool sim_only = false;                 // stop after the similarity kernel
   int32_t *ms = nullptr, *mt = nullptr;
   char *moves_dev = nullptr; // device buffer for paths
   int64_t moves_base = 0;    // offset of this chunk's first pair in moves_dev
@@ -60,6 +64,8 @@ LexDev lex_dev(const ym_lexicon *L);
 ym_status check_params(const ym_params *p);
 ym_status check_doc_off(const int64_t *o, int64_t n_pairs, const char *what);
 ym_status ensure_table(ym_ctx *c, const ym_params *p, hipStream_t st);
+// Resolve the batch's source tokens into `head` (trans_bytes(n_src_tok) bytes) and point b.trans at it.
+ym_status translate_batch(ym_ctx *c, const ym_lexicon *L, DevBatch &b, char *head, hipStream_t st);
 ym_status plan_chunks(const int64_t *sdo, const int64_t *tdo, int64_t n_pairs, size_t ws_bytes,
                       std::vector<std::pair<int64_t, int64_t>> &chunks);
 // Pinned staging buffer for plan uploads and the event that marks its last

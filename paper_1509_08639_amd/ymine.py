@@ -99,9 +99,9 @@ def lib():
     L.ym_result_free.restype = None
     L.ym_mine_device_capacity.argtypes = [P(i64), P(i64), i64]
     L.ym_mine_device_capacity.restype = i64
-    L.ym_mine_device_workspace.argtypes = [P(i64), P(i64), i64]
+    L.ym_mine_device_workspace.argtypes = [P(i64), P(i64), i64, i64]
     L.ym_mine_device_workspace.restype = C.c_size_t
-    L.ym_mine_device_workspace_min.argtypes = [P(i64), P(i64), i64]
+    L.ym_mine_device_workspace_min.argtypes = [P(i64), P(i64), i64, i64]
     L.ym_mine_device_workspace_min.restype = C.c_size_t
     L.ym_mine_device.argtypes = [vp, vp, P(DeviceBatch), P(Params), vp, C.c_size_t, P(DeviceOut), vp]
     L.ym_similarity.argtypes = [vp, vp, P(Batch), P(Params), P(f32), P(i32), P(i32)]
@@ -197,10 +197,10 @@ class Context:
 
     def profile_read(self):
         """{kernel: (ms summed, launches)} since the last read."""
-        ms = (C.c_double * 3)()
-        n = (i64 * 3)()
+        ms = (C.c_double * 4)()
+        n = (i64 * 4)()
         _check(lib().ym_profile_read(self.h, ms, n))
-        return {k: (ms[i], n[i]) for i, k in enumerate(("similarity", "nw", "compact"))}
+        return {k: (ms[i], n[i]) for i, k in enumerate(("similarity", "nw", "compact", "translate"))}
 
     def lexicon(self, src_ids, off, tgt_ids) -> "Lexicon":
         return Lexicon(self, src_ids, off, tgt_ids)
@@ -305,7 +305,8 @@ class DeviceMiner:
         self.d_ttok = t(corpus.tgt_tok, np.int32)
         L = lib()
         self.cap = int(L.ym_mine_device_capacity(_ptr(self.sdo, i64), _ptr(self.tdo, i64), self.n_pairs))
-        full = int(L.ym_mine_device_workspace(_ptr(self.sdo, i64), _ptr(self.tdo, i64), self.n_pairs))
+        full = int(L.ym_mine_device_workspace(_ptr(self.sdo, i64), _ptr(self.tdo, i64), self.n_pairs,
+                                              int(corpus.src_tok.shape[0])))
         self.ws_bytes = full if workspace_bytes is None else int(workspace_bytes)
         self.ws = torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8, device=device)
         self.pair_off = torch.zeros(self.n_pairs + 1, dtype=torch.int64, device=device)

@@ -157,8 +157,9 @@ def test_device_and_per_pair_forms_match(ym, ctx, O):
     dm = ym.DeviceMiner(ctx, L, c)
     dm.run(w, -0.2, 0.5)
     d = dm.result()
-    # a small workspace forces several chunks
-    dm2 = ym.DeviceMiner(ctx, L, c, workspace_bytes=2 << 20)
+    # a small workspace forces several chunks (token translations + 2 MiB)
+    head = (c.src_tok.size * 16 + 255) // 256 * 256
+    dm2 = ym.DeviceMiner(ctx, L, c, workspace_bytes=head + (2 << 20))
     dm2.run(w, -0.2, 0.5)
     e = dm2.result()
     for r in (b, d, e):
