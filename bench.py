@@ -61,6 +61,109 @@ def workload_stats(corpus, lex):
                 src_tokens=int(corpus.src_tok.size), tgt_tokens=int(corpus.tgt_tok.size))
 
 
+def served(ctx_cls, ymine, synth, seconds, rate, log_every=2.0):
+    """Poisson arrivals of single document pairs (the served workload) replayed in
+    real time against (a) the continuous-batching server and (b) the plain
+    per-pair GPU form, FIFO, one request at a time.  Latency = completion minus
+    scheduled arrival."""
+    import threading
+    cfg = synth.CONFIGS[3]
+    n_req = int(seconds * rate)
+    lex = synth.make_lexicon(cfg)
+    corp = synth.generate(cfg, lex, pair_ids=np.arange(n_req))
+    w = synth.weights(cfg.seed)
+    arr = synth.arrivals(cfg.seed, rate, n_req)
+    reqs = [ymine.prepare(corp.slice(k, k + 1)) for k in range(n_req)]
+    n, m = corp.nm()
+    ctx = ctx_cls(0)
+    L = ctx.lexicon(lex.src_ids, lex.off, lex.tgt_ids)
+    prm = ymine.params(w, -0.2, 0.5)
+    out = {}
+
+    # (a) server
+    srv = ymine.Server(ctx, L, w, -0.2, 0.5, max_pairs_per_step=512, max_cells_per_step=1 << 25)
+    ymine.mine_prepared(ctx, L, reqs[0], prm)  # warm the kernels
+    done_ns = np.zeros(n_req, np.int64)
+    ticket_of = {}
+    lock = threading.Lock()
+    t0 = time.monotonic_ns() + 200_000_000
+
+    def submitter():
+        for k in range(n_req):
+            due = t0 + int(arr[k] * 1e9)
+            while True:
+                now = time.monotonic_ns()
+                if now >= due:
+                    break
+                time.sleep(min((due - now) / 1e9, 0.0005))
+            t = srv.submit_prepared(reqs[k])
+            with lock:
+                ticket_of[t] = k
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    got = 0
+    results_srv = {}
+    last = time.time()
+    while got < n_req:
+        r = srv.next_done(1_000_000)
+        if r is None:
+            continue
+        t, dn = r
+        with lock:
+            k = ticket_of.get(t)
+        while k is None:
+            time.sleep(0.0001)
+            with lock:
+                k = ticket_of.get(t)
+        res = srv.poll(t, 0)
+        done_ns[k] = dn
+        if k % 97 == 0:
+            results_srv[k] = res
+        got += 1
+        if time.time() - last > log_every:
+            log(f"[serve] server: {got}/{n_req} done")
+            last = time.time()
+    th.join()
+    stats = srv.stats()
+    srv.stop()
+    lat = (done_ns - (t0 + (arr * 1e9).astype(np.int64))) / 1e6
+    span = (done_ns.max() - t0) / 1e9
+    out["server"] = dict(p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
+                         mean_ms=float(lat.mean()), max_ms=float(lat.max()), throughput_pairs_per_s=n_req / span,
+                         steps=stats["steps"], pairs_per_step=stats["completed"] / max(stats["steps"], 1))
+    log(f"[serve] server {out['server']}")
+
+    # (b) plain per-pair GPU form, FIFO on the same trace (bounded to the same wall time + 20 s)
+    lat_pp = []
+    same = True
+    t0b = time.monotonic_ns() + 100_000_000
+    deadline = t0b + int((seconds + 20) * 1e9)
+    for k in range(n_req):
+        due = t0b + int(arr[k] * 1e9)
+        now = time.monotonic_ns()
+        if now < due:
+            time.sleep((due - now) / 1e9)
+        res = ymine.mine_prepared(ctx, L, reqs[k], prm, per_pair=True)
+        fin = time.monotonic_ns()
+        lat_pp.append((fin - due) / 1e6)
+        if k in results_srv:
+            same &= all(np.array_equal(res[x], results_srv[k][x]) for x in res)
+        if fin > deadline:
+            break
+    lat_pp = np.array(lat_pp)
+    out["plain_per_pair"] = dict(p50_ms=float(np.percentile(lat_pp, 50)), p99_ms=float(np.percentile(lat_pp, 99)),
+                                 mean_ms=float(lat_pp.mean()), completed=int(lat_pp.size),
+                                 throughput_pairs_per_s=lat_pp.size / ((time.monotonic_ns() - t0b) / 1e9))
+    out["results_identical_on_sample"] = bool(same)
+    out["workload"] = dict(name=cfg.name, requests=n_req, rate_per_s=rate, seconds=seconds,
+                           cells=int((n * m).sum()), max_cells=int((n * m).max()))
+    log(f"[serve] plain per-pair {out['plain_per_pair']}")
+    L.close()
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -69,6 +172,8 @@ def main():
     ap.add_argument("--workload", type=int, default=1, help="workload index (default: the 10k-pair batch)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample (0: skip)")
     ap.add_argument("--per-pair-sample", type=int, default=1000, help="pairs timed in the plain per-pair form")
+    ap.add_argument("--serve-seconds", type=float, default=5.0, help="length of the served arrival trace (0: skip)")
+    ap.add_argument("--serve-rate", type=float, default=2000.0, help="Poisson arrival rate of the served trace")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates the HBM byte counters) and exit")
     args = ap.parse_args()
@@ -191,6 +296,10 @@ def main():
                    sample=f"first {done} pairs of the {corpus.n_pairs}-pair batch, single thread, {el:.1f} s")
         log(f"[bench] cpu oracle: {cpu}")
 
+    serve = None
+    if args.serve_seconds > 0:
+        serve = served(ymine.Context, ymine, synth, args.serve_seconds, args.serve_rate)
+
     line = {
         "metric": METRIC,
         "value": pairs_per_s,
@@ -212,6 +321,7 @@ def main():
         "kernels": kern,
         "roofline": roof,
         "plain_per_pair": plain,
+        "served": serve,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

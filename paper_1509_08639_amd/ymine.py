@@ -155,6 +155,18 @@ class _HostBatch:
                        _ptr(a[3], i64), _ptr(a[4], i64), _ptr(a[5], i32))
 
 
+def prepare(corpus):
+    """Pack a corpus into ctypes form once (for repeated or timed submission)."""
+    return _HostBatch(corpus)
+
+
+def mine_prepared(ctx: Context, lex: Lexicon, hb, p: Params, per_pair: bool = False) -> dict:
+    rp = P(Result)()
+    fn = lib().ym_mine_per_pair if per_pair else lib().ym_mine
+    _check(fn(ctx.h, lex.h, C.byref(hb.b), C.byref(p), C.byref(rp)))
+    return _result_to_numpy(rp)
+
+
 def _result_to_numpy(rp) -> dict:
     r = rp.contents
     n, k = r.n_pairs, r.n_out
@@ -348,7 +360,10 @@ class Server:
         ctx._deps.add(self)
 
     def submit(self, corpus_one_pair) -> int:
-        hb = _HostBatch(corpus_one_pair)
+        return self.submit_prepared(prepare(corpus_one_pair))
+
+    def submit_prepared(self, hb) -> int:
+        """Submit a request packed beforehand with prepare()."""
         t = u64()
         _check(lib().ym_submit(self.h, C.byref(hb.b), C.byref(t)))
         return t.value

@@ -181,6 +181,16 @@ class Corpus:
         return (side(self.src_doc_off, self.src_sent_off, self.src_tok),
                 side(self.tgt_doc_off, self.tgt_sent_off, self.tgt_tok))
 
+    def slice(self, p0: int, p1: int) -> "Corpus":
+        """Pairs [p0, p1) as a new packed corpus (array slices, rebased offsets)."""
+        def side(doc, sent, tok):
+            s0, s1 = int(doc[p0]), int(doc[p1])
+            t0, t1 = int(sent[s0]), int(sent[s1])
+            return doc[p0:p1 + 1] - s0, sent[s0:s1 + 1] - t0, tok[t0:t1].copy()
+        a = side(self.src_doc_off, self.src_sent_off, self.src_tok)
+        b = side(self.tgt_doc_off, self.tgt_sent_off, self.tgt_tok)
+        return Corpus(a[0], a[1], a[2], b[0], b[1], b[2])
+
     def subset(self, pairs) -> "Corpus":
         """A new packed corpus holding the listed pairs, in that order."""
         srcs, tgts = [], []
