@@ -47,8 +47,11 @@ ym_status check_host_batch(const ym_batch *b, HostBatchInfo &info) {
   if (info.n_src_tok > 0 && !b->src_tok) return fail(YM_EINVAL, "src_tok is NULL");
   if (info.n_tgt_tok > 0 && !b->tgt_tok) return fail(YM_EINVAL, "tgt_tok is NULL");
   for (int64_t s2 = 0; s2 < info.n_tgt_sent; s2++)
-    if (b->tgt_sent_off[s2 + 1] - b->tgt_sent_off[s2] > kTcap)
-      return fail(YM_EINVAL, "target sentence %lld has more than %d tokens", (long long)s2, kTcap);
+    if (b->tgt_sent_off[s2 + 1] - b->tgt_sent_off[s2] > kMaxSentTokens)
+      return fail(YM_EINVAL, "target sentence %lld has more than %d tokens", (long long)s2, kMaxSentTokens);
+  for (int64_t s2 = 0; s2 < info.n_src_sent; s2++)
+    if (b->src_sent_off[s2 + 1] - b->src_sent_off[s2] > kMaxSentTokens)
+      return fail(YM_EINVAL, "source sentence %lld has more than %d tokens", (long long)s2, kMaxSentTokens);
   return YM_OK;
 }
 

@@ -226,7 +226,7 @@ __device__ __forceinline__ int64_t score_pos_fast(int i, int c, int n, int m) {
   return score_pos(i, c, n, m);
 }
 
-__global__ __launch_bounds__(kSimThreads) void sim_kernel(SimArgs a) {
+__global__ __launch_bounds__(kSimThreads, 4) void sim_kernel(SimArgs a) {
   __shared__ int32_t ukey[kUcap];
   __shared__ uint16_t ulid[kUcap];
   __shared__ __align__(16) uint16_t tdoc[kTdocCap];
@@ -391,6 +391,382 @@ __global__ __launch_bounds__(kSimThreads) void sim_kernel(SimArgs a) {
             a.mt_out[cell] = mt;
           }
         }
+      }
+      __syncthreads();
+      j0 = j1;
+    }
+  }
+}
+
+// --------------------------------------------- (a) similarity, bit-sliced tiles
+// The tile kernel computes the same counts as sim_kernel with far fewer
+// instructions per cell.  A work item is (pair, source rows [i0, i1)) with i0
+// a multiple of 128; wave w owns the 64-row strip starting at i0 + 64 w.
+// Target sentences are taken in chunks of at most 64 sentences / kTcap
+// tokens, staged in LDS with dense local ids as in sim_kernel, plus
+//   D[id] = set of the chunk's target sentences holding id (64-bit word).
+// For its strip a wave builds
+//   B[id] = set of the strip's source sentences whose X_i holds id,
+// and counts with bit-sliced counters (plane b holds bit b of 64 counts):
+//   source pass, lane = source sentence i: for each token q, the OR of
+//     D[id] over the token's translations is the set of target sentences j
+//     that meet T(s_i[q]); adding it counts m_s(i, .) for all 64 j at once;
+//   target pass, lane = target sentence j: for each token p, B[id(t_j[p])]
+//     is the set of source sentences i with t_j[p] in X_i; adding it counts
+//     m_t(., j) for all 64 i at once.
+// A 64 x 64 bit-matrix transpose through lane shuffles turns the m_s planes
+// around so that lane j holds both counts of its 64 cells, scores them and
+// stores them.
+constexpr int kTileWaves = 2;
+constexpr int kTileThreads = 64 * kTileWaves;
+constexpr int kFastPlanes = 6;   // counts <= 63 (sentences of at most 63 tokens)
+constexpr int kWidePlanes = 11;  // counts <= 2047
+
+template <int NW>
+__device__ __forceinline__ int block_excl_sum(int v, int *sh, int *total) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) sh[wv] = x;
+  __syncthreads();
+  int base = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < NW; w++) {
+    const int s = sh[w];
+    base += (w < wv) ? s : 0;
+    tot += s;
+  }
+  __syncthreads();
+  *total = tot;
+  return base + x - v;
+}
+
+// add a 64-bit set (one bit per counter) into NPL bit-sliced planes
+template <int NPL>
+__device__ __forceinline__ void bs_add(uint32_t (&lo)[NPL], uint32_t (&hi)[NPL], uint32_t xl, uint32_t xh) {
+#pragma unroll
+  for (int b = 0; b < NPL; b++) {
+    const uint32_t tl = lo[b] & xl, th = hi[b] & xh;
+    lo[b] ^= xl;
+    hi[b] ^= xh;
+    xl = tl;
+    xh = th;
+  }
+}
+
+// transpose a 64 x 64 bit matrix held one row per lane (bit c of lane l's
+// word = M[l][c]); afterwards lane c holds column c (bit l = M[l][c])
+__device__ __forceinline__ void transpose64(uint32_t &lo, uint32_t &hi, int lane) {
+  {
+    const uint32_t ylo = __shfl_xor(lo, 32), yhi = __shfl_xor(hi, 32);
+    const bool up = (lane & 32) != 0;
+    lo = up ? yhi : lo;
+    hi = up ? hi : ylo;
+  }
+#pragma unroll
+  for (int s = 16; s >= 1; s >>= 1) {
+    const uint32_t m = s == 16 ? 0x0000FFFFu : s == 8 ? 0x00FF00FFu : s == 4 ? 0x0F0F0F0Fu : s == 2 ? 0x33333333u : 0x55555555u;
+    const uint32_t ylo = __shfl_xor(lo, s), yhi = __shfl_xor(hi, s);
+    const bool up = (lane & s) != 0;
+    const uint32_t alo = (lo & m) | ((ylo & m) << s), ahi = (hi & m) | ((yhi & m) << s);
+    const uint32_t blo = (lo & ~m) | ((ylo & ~m) >> s), bhi = (hi & ~m) | ((yhi & ~m) >> s);
+    lo = up ? blo : alo;
+    hi = up ? bhi : ahi;
+  }
+}
+
+template <int NPL>
+__device__ __forceinline__ uint32_t bs_get(const uint32_t (&lo)[NPL], const uint32_t (&hi)[NPL], int l) {
+  uint32_t v = 0;
+#pragma unroll
+  for (int b = 0; b < NPL; b++) v |= ((l < 32 ? lo[b] >> l : hi[b] >> (l - 32)) & 1u) << b;
+  return v;
+}
+
+struct TileCtx {
+  const int32_t *ukey;
+  const uint16_t *ulid;
+  const uint64_t *D;
+  uint64_t *B;
+  const uint16_t *tp;  // this lane's staged target ids
+  int bl;              // this lane's target sentence length
+  bool jok;
+  int nj, j0, nlid;
+};
+
+// One strip x chunk tile: counts and scores of rows [r0, r0 + R) against the
+// chunk's target sentences.
+template <int NPL>
+__device__ __forceinline__ void tile_work(const SimArgs &a, const PairDesc &d, const int64_t *soffs, int r0, int R,
+                                          const TileCtx &t, int lane, int *al_s) {
+  uint64_t *B = t.B;
+  // clear B
+  for (int k = lane; k < t.nlid; k += 64) B[k] = 0;
+  wave_sync();
+
+  // ---- source pass: lane = source sentence r0 + lane
+  const bool iok = lane < R;
+  int64_t sb = 0;
+  int al = 0;
+  if (iok) {
+    sb = clamp64(soffs[r0 + lane], 0, a.n_src_tok);
+    const int64_t se = clamp64(soffs[r0 + lane + 1], sb, a.n_src_tok);
+    al = (int)min<int64_t>(se - sb, 0x7fffffff);
+  }
+  const int maxa = wave_max(al);
+  uint32_t sl[NPL], sh[NPL];
+#pragma unroll
+  for (int b = 0; b < NPL; b++) sl[b] = sh[b] = 0;
+  const uint64_t mybit = 1ull << lane;
+  int4 nxt = al > 0 ? a.trans[sb] : make_int4(-1, -1, -1, -1);
+  for (int q = 0; q < maxa; q++) {
+    const int4 t4 = nxt;
+    nxt = q + 1 < al ? a.trans[sb + q + 1] : make_int4(-1, -1, -1, -1);
+    uint64_t C = 0;
+    if (q < al) {
+      if (t4.x == -2) {
+        for (int e = 0; e < t4.z; e++) {
+          const int s = u_find(t.ukey, a.lex.vals[t4.y + e]);
+          if (s >= 0) {
+            const int id = t.ulid[s];
+            atomicOr(reinterpret_cast<unsigned long long *>(&B[id]), (unsigned long long)mybit);
+            C |= t.D[id];
+          }
+        }
+      } else {
+        const int s0 = u_find(t.ukey, t4.x), s1 = u_find(t.ukey, t4.y), s2 = u_find(t.ukey, t4.z),
+                  s3 = u_find(t.ukey, t4.w);
+        const int id0 = s0 >= 0 ? t.ulid[s0] : 0, id1 = s1 >= 0 ? t.ulid[s1] : 0;
+        const int id2 = s2 >= 0 ? t.ulid[s2] : 0, id3 = s3 >= 0 ? t.ulid[s3] : 0;
+        if (id0) atomicOr(reinterpret_cast<unsigned long long *>(&B[id0]), (unsigned long long)mybit);
+        if (id1) atomicOr(reinterpret_cast<unsigned long long *>(&B[id1]), (unsigned long long)mybit);
+        if (id2) atomicOr(reinterpret_cast<unsigned long long *>(&B[id2]), (unsigned long long)mybit);
+        if (id3) atomicOr(reinterpret_cast<unsigned long long *>(&B[id3]), (unsigned long long)mybit);
+        C = (t.D[id0] | t.D[id1]) | (t.D[id2] | t.D[id3]);  // D[0] = 0
+      }
+    }
+    bs_add<NPL>(sl, sh, (uint32_t)C, (uint32_t)(C >> 32));
+  }
+  wave_sync();
+
+  // ---- target pass: lane = target sentence j0 + lane
+  uint32_t tl[NPL], th[NPL];
+#pragma unroll
+  for (int b = 0; b < NPL; b++) tl[b] = th[b] = 0;
+  const int maxb = wave_max(t.bl);
+  for (int k = 0; k < maxb; k += 4) {
+    uint64_t x0 = 0, x1 = 0, x2 = 0, x3 = 0;
+    if (k < t.bl) {  // ids are padded to a multiple of 4 with id 0 (B[0] = 0)
+      const uint2 ids = *reinterpret_cast<const uint2 *>(t.tp + k);
+      x0 = B[ids.x & 0xFFFFu];
+      x1 = B[ids.x >> 16];
+      x2 = B[ids.y & 0xFFFFu];
+      x3 = B[ids.y >> 16];
+    }
+    bs_add<NPL>(tl, th, (uint32_t)x0, (uint32_t)(x0 >> 32));
+    bs_add<NPL>(tl, th, (uint32_t)x1, (uint32_t)(x1 >> 32));
+    bs_add<NPL>(tl, th, (uint32_t)x2, (uint32_t)(x2 >> 32));
+    bs_add<NPL>(tl, th, (uint32_t)x3, (uint32_t)(x3 >> 32));
+  }
+
+  // ---- bring m_s(i, j) to lane j
+#pragma unroll
+  for (int b = 0; b < NPL; b++) transpose64(sl[b], sh[b], lane);
+
+  // ---- score the 64 cells of lane j: rows r0 .. r0 + R - 1
+  al_s[lane] = al;  // source lengths, read back with a uniform index
+  wave_sync();
+  const int n = d.n, m = d.m;
+  const int c = t.j0 + lane;
+  if (NPL == kFastPlanes && m < 65000) {
+    // Cells l0 + 8k (k = 0..3) of a 32-row half at once: one shift and mask
+    // per plane gathers their bits into four bytes.  Four cursors follow the
+    // diagonals l0 + 8k + c of the strip-diagonal layout.
+    auto tri32 = [](int x) -> uint32_t { return x > 0 ? (uint32_t)x * (uint32_t)(x + 1) / 2u : 0u; };
+    auto delta = [&](int tt) -> uint32_t { return tri32(tt) - tri32(tt - R) - tri32(tt - m) + tri32(tt - R - m); };
+    auto cnt = [&](int tt) -> uint32_t { return (uint32_t)max(0, min(R - 1, tt) - max(0, tt - m + 1) + 1); };
+    float *strip = a.S + d.s_off + (int64_t)r0 * m;
+    const uint32_t bl6 = (uint32_t)t.bl << (2 * kLogTabLen);
+    for (int h = 0; h < 2; h++) {
+      if (32 * h >= R) break;
+      uint32_t cur[4];
+#pragma unroll
+      for (int k = 0; k < 4; k++) cur[k] = delta(32 * h + 8 * k + c);
+      for (int l0 = 0; l0 < 8; l0++) {
+        uint32_t ms4 = 0, mt4 = 0;
+#pragma unroll
+        for (int b = 0; b < NPL; b++) {
+          const uint32_t ws = h ? sh[b] : sl[b], wt = h ? th[b] : tl[b];
+          ms4 |= ((ws >> l0) & 0x01010101u) << b;
+          mt4 |= ((wt >> l0) & 0x01010101u) << b;
+        }
+        float sv[4];
+        int64_t pos[4];
+        bool ok[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+          const int l = 32 * h + l0 + 8 * k;
+          const int tt = l + c;
+          ok[k] = t.jok && l < R;
+          const uint32_t ai = (uint32_t)al_s[min(l, 63)];
+          const uint32_t ms = (ms4 >> (8 * k)) & 0xFFu, mt = (mt4 >> (8 * k)) & 0xFFu;
+          const uint32_t idx = ((ai << (3 * kLogTabLen)) | bl6) | (ms << kLogTabLen) | mt;
+          sv[k] = ok[k] ? a.table[idx] : 0.0f;
+          pos[k] = (int64_t)cur[k] + l - max(0, tt - m + 1);
+          cur[k] += cnt(tt);
+          if (ok[k] && a.ms_out) {
+            const int64_t cell = d.s_off + (int64_t)(r0 + l) * m + c;
+            a.ms_out[cell] = (int32_t)ms;
+            a.mt_out[cell] = (int32_t)mt;
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < 4; k++)
+          if (ok[k]) strip[pos[k]] = sv[k];
+      }
+    }
+  } else {
+    for (int l = 0; l < R; l++) {
+      const int ai = al_s[l];
+      if (t.jok) {
+        const int ms = (int)bs_get<NPL>(sl, sh, l), mt = (int)bs_get<NPL>(tl, th, l);
+        const float sv = (ai < kTabLen && t.bl < kTabLen)
+                             ? a.table[(((ai << kLogTabLen) | t.bl) << (2 * kLogTabLen)) | (ms << kLogTabLen) | mt]
+                             : score_direct(a.w0, a.w1, a.w2, a.w3, ms, ai, mt, t.bl);
+        a.S[d.s_off + score_pos(r0 + l, c, n, m)] = sv;
+        if (a.ms_out) {
+          const int64_t cell = d.s_off + (int64_t)(r0 + l) * m + c;
+          a.ms_out[cell] = ms;
+          a.mt_out[cell] = mt;
+        }
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(kTileThreads) void sim_tile_kernel(SimArgs a) {
+  __shared__ int32_t ukey[kUcap];
+  __shared__ uint16_t ulid[kUcap];
+  __shared__ __align__(16) uint16_t tdoc[kTdocCap];
+  __shared__ uint8_t tsen[kTdocCap];
+  __shared__ uint16_t toff[kJcap];
+  __shared__ uint16_t toff_o[kJcap + 1];
+  __shared__ uint16_t tlen[kJcap];
+  __shared__ uint64_t Dw[kTcap + 4];
+  __shared__ uint64_t Bw[kTileWaves][kTcap + 4];
+  __shared__ int alw[kTileWaves][64];
+  __shared__ int sh_scan[kTileWaves];
+  __shared__ int sh_j1;
+
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+
+  for (int64_t item = blockIdx.x; item < a.n_items; item += gridDim.x) {
+    const SimItem it = a.items[item];
+    const PairDesc d = a.descs[it.pair];
+    const int m = d.m;
+    if (m <= 0 || it.i1 <= it.i0) continue;
+    const int64_t *toffs = a.tgt_sent_off + d.tgt_sent0;
+    const int64_t *soffs = a.src_sent_off + d.src_sent0;
+    const int r0 = it.i0 + 64 * wv;
+    const int R = max(0, min(64, it.i1 - r0));
+
+    for (int j0 = 0; j0 < m;) {
+      if (tid == 0) {
+        const int64_t base = clamp64(toffs[j0], 0, a.n_tgt_tok);
+        int lo = j0 + 1, hi = min(m, j0 + kJcap);
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (clamp64(toffs[mid], 0, a.n_tgt_tok) - base <= kTcap)
+            lo = mid;
+          else
+            hi = mid - 1;
+        }
+        sh_j1 = lo;
+      }
+      for (int s = tid; s < kUcap; s += kTileThreads) ukey[s] = kEmpty;
+      __syncthreads();
+      const int j1 = sh_j1;
+      const int nj = j1 - j0;
+      const int64_t tbase = clamp64(toffs[j0], 0, a.n_tgt_tok);
+      const int ntok = (int)clamp64(clamp64(toffs[j1], 0, a.n_tgt_tok) - tbase, 0, kTcap);
+      int blen = 0;
+      if (tid < nj) {
+        const int ostart = (int)clamp64(clamp64(toffs[j0 + tid], 0, a.n_tgt_tok) - tbase, 0, ntok);
+        const int oend = (int)clamp64(clamp64(toffs[j0 + tid + 1], 0, a.n_tgt_tok) - tbase, ostart, ntok);
+        blen = oend - ostart;
+        toff_o[tid] = (uint16_t)ostart;
+        tlen[tid] = (uint16_t)blen;
+      }
+      int npad;
+      const int pstart = block_excl_sum<kTileWaves>((blen + 3) & ~3, sh_scan, &npad);
+      if (tid < nj) toff[tid] = (uint16_t)pstart;
+      if (tid == 0) toff_o[nj] = (uint16_t)ntok;
+      for (int q = tid; q < npad; q += kTileThreads) tdoc[q] = 0xFFFF;
+      __syncthreads();
+      for (int p = tid; p < ntok; p += kTileThreads) {
+        int lo = 0, hi = nj - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (toff_o[mid] <= p)
+            lo = mid;
+          else
+            hi = mid - 1;
+        }
+        const int32_t x = a.tgt_tok[tbase + p];
+        const int q = toff[lo] + (p - toff_o[lo]);
+        tdoc[q] = x < 0 ? (uint16_t)0xFFFF : (uint16_t)u_insert(ukey, x);
+        tsen[q] = (uint8_t)lo;
+      }
+      __syncthreads();
+      constexpr int kSpt = kUcap / kTileThreads;
+      int cnt = 0;
+#pragma unroll
+      for (int k = 0; k < kSpt; k++) cnt += (ukey[tid * kSpt + k] != kEmpty);
+      int total;
+      int r = block_excl_sum<kTileWaves>(cnt, sh_scan, &total);
+#pragma unroll
+      for (int k = 0; k < kSpt; k++) {
+        const int s = tid * kSpt + k;
+        if (ukey[s] != kEmpty) ulid[s] = (uint16_t)(1 + r++);
+      }
+      const int nlid = total + 1;
+      for (int k = tid; k < nlid; k += kTileThreads) Dw[k] = 0;
+      __syncthreads();
+      for (int q = tid; q < npad; q += kTileThreads) {
+        const uint16_t s = tdoc[q];
+        const uint16_t id = s == 0xFFFF ? (uint16_t)0 : ulid[s];
+        tdoc[q] = id;
+        if (id) atomicOr(reinterpret_cast<unsigned long long *>(&Dw[id]), 1ull << tsen[q]);
+      }
+      __syncthreads();
+
+      if (R > 0) {
+        TileCtx tc;
+        tc.ukey = ukey;
+        tc.ulid = ulid;
+        tc.D = Dw;
+        tc.B = Bw[wv];
+        tc.jok = lane < nj;
+        tc.bl = tc.jok ? tlen[lane] : 0;
+        tc.tp = tdoc + (tc.jok ? toff[lane] : 0);
+        tc.nj = nj;
+        tc.j0 = j0;
+        tc.nlid = nlid;
+        // counts above 63 need the wide planes (sentences over 63 tokens)
+        int al = 0;
+        if (lane < R) {
+          const int64_t b0 = clamp64(soffs[r0 + lane], 0, a.n_src_tok);
+          al = (int)min<int64_t>(clamp64(soffs[r0 + lane + 1], b0, a.n_src_tok) - b0, 0x7fffffff);
+        }
+        const bool wide = wave_max(max(al, tc.bl)) > 63;
+        if (wide)
+          tile_work<kWidePlanes>(a, d, soffs, r0, R, tc, lane, alw[wv]);
+        else
+          tile_work<kFastPlanes>(a, d, soffs, r0, R, tc, lane, alw[wv]);
       }
       __syncthreads();
       j0 = j1;
@@ -727,9 +1103,12 @@ hipError_t launch_score_table(float w0, float w1, float w2, float w3, float *tab
   return hipGetLastError();
 }
 
-hipError_t launch_similarity(const SimArgs &a, int grid, hipStream_t st) {
+hipError_t launch_similarity(const SimArgs &a, int grid, int variant, hipStream_t st) {
   if (a.n_items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(sim_kernel, dim3(grid), dim3(kSimThreads), 0, st, a);
+  if (variant == 0)
+    hipLaunchKernelGGL(sim_tile_kernel, dim3(grid), dim3(kTileThreads), 0, st, a);
+  else
+    hipLaunchKernelGGL(sim_kernel, dim3(grid), dim3(kSimThreads), 0, st, a);
   return hipGetLastError();
 }
 

@@ -14,6 +14,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -233,6 +234,10 @@ ym_status ym_create(int device, size_t hbm_budget_bytes, ym_ctx **out) {
   ym_ctx *c = new (std::nothrow) ym_ctx();
   if (!c) return fail(YM_ENOMEM, "context allocation");
   c->device = device;
+  {
+    const char *v = getenv("YM_SIM_KERNEL");
+    c->sim_variant = (v && std::strcmp(v, "tile") == 0) ? 0 : 1;
+  }
   if ((e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking)) != hipSuccess) {
     delete c;
     return hip_fail(e, "hipStreamCreate");
@@ -546,7 +551,7 @@ ym_status run_chunk(ym_ctx *c, const ym_lexicon *L, const DevBatch &b, const ym_
     const int grid = (int)std::min<int64_t>(ch.n_items, (int64_t)1 << 30);
     {
       KernelTimer kt(c, 0, st);
-      e = launch_similarity(a, grid, st);
+      e = launch_similarity(a, grid, c->sim_variant, st);
     }
     if (e != hipSuccess) return hip_fail(e, "similarity kernel");
     if (dbg && dbg->S_rowmajor_out &&

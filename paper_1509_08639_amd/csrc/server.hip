@@ -379,12 +379,15 @@ ym_status ym_submit(ym_server *S, const ym_batch *b, uint64_t *ticket) {
   const int64_t n = b->src_doc_off[1], m = b->tgt_doc_off[1];
   if (!b->src_sent_off || !b->tgt_sent_off) return fail(YM_EINVAL, "NULL sentence offsets");
   if (b->src_sent_off[0] != 0 || b->tgt_sent_off[0] != 0) return fail(YM_EINVAL, "sentence offsets must start at 0");
-  for (int64_t i = 0; i < n; i++)
+  for (int64_t i = 0; i < n; i++) {
     if (b->src_sent_off[i + 1] < b->src_sent_off[i]) return fail(YM_EINVAL, "src_sent_off decreases");
+    if (b->src_sent_off[i + 1] - b->src_sent_off[i] > kMaxSentTokens)
+      return fail(YM_EINVAL, "source sentence %lld has more than %d tokens", (long long)i, kMaxSentTokens);
+  }
   for (int64_t j = 0; j < m; j++) {
     if (b->tgt_sent_off[j + 1] < b->tgt_sent_off[j]) return fail(YM_EINVAL, "tgt_sent_off decreases");
-    if (b->tgt_sent_off[j + 1] - b->tgt_sent_off[j] > kTcap)
-      return fail(YM_EINVAL, "target sentence %lld has more than %d tokens", (long long)j, kTcap);
+    if (b->tgt_sent_off[j + 1] - b->tgt_sent_off[j] > kMaxSentTokens)
+      return fail(YM_EINVAL, "target sentence %lld has more than %d tokens", (long long)j, kMaxSentTokens);
   }
   const int64_t ns = b->src_sent_off[n], nt = b->tgt_sent_off[m];
   if ((ns && !b->src_tok) || (nt && !b->tgt_tok)) return fail(YM_EINVAL, "NULL tokens");

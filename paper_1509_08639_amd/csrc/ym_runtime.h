@@ -92,6 +92,7 @@ struct ym_ctx {
   ym::HostBuf host_out;
   float table_w[4] = {0, 0, 0, 0};
   bool table_valid = false;
+  int sim_variant = 1;  // similarity kernel: 1 lane per target sentence (default), 0 bit-sliced tiles (YM_SIM_KERNEL=tile)
   // kernel timing
   bool prof = false;
   std::mutex prof_mu;

@@ -244,7 +244,37 @@ def test_errors(ym, ctx):
     long_t = synth.from_lists([[[1]]], [[np.zeros(1025, np.int32)]])
     with pytest.raises(ym.YmError):
         ym.mine(ctx, L, long_t, [0, 0, 0, 0], -0.2, 0.5)
+    long_s = synth.from_lists([[np.zeros(1025, np.int32)]], [[[1]]])
+    with pytest.raises(ym.YmError):
+        ym.mine(ctx, L, long_s, [0, 0, 0, 0], -0.2, 0.5)
     # empty batch
     empty = synth.from_lists([], [])
     r = ym.mine(ctx, L, empty, [0, 0, 0, 0], -0.2, 0.5)
     assert r["pair_off"].tolist() == [0]
+
+
+@pytest.mark.parametrize("seed", [5, 6])
+def test_similarity_variants_agree(ym, O, seed):
+    """The bit-sliced tile kernel and the lane-per-sentence kernel give the
+    same counts and scores (both also match the oracle above)."""
+    import os
+    lex = parity.random_lexicon(seed, vocab=90)
+    c = parity.random_corpus(seed, n_pairs=10, nmax=140, mmax=150, lmax_src=70, lmax_tgt=66)
+    w = np.array([-2.0, 3.0, 2.5, 0.75], np.float32)
+    outs = []
+    for variant in ("tile", "lanes"):
+        old = os.environ.get("YM_SIM_KERNEL")
+        os.environ["YM_SIM_KERNEL"] = variant
+        try:
+            cx = ym.Context(0)
+        finally:
+            if old is None:
+                os.environ.pop("YM_SIM_KERNEL")
+            else:
+                os.environ["YM_SIM_KERNEL"] = old
+        L = cx.lexicon(lex.src_ids, lex.off, lex.tgt_ids)
+        outs.append(ym.similarity(cx, L, c, w))
+        L.close()
+        cx.close()
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
