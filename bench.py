@@ -280,7 +280,7 @@ def main():
         log(f"[bench] plain per-pair: {plain}")
 
     # CPU oracle on a bounded sample of the same workload
-    cpu = None
+    cpu = cpu_mt = None
     if args.cpu_seconds > 0:
         import oracle
         O = oracle.default()
@@ -295,6 +295,16 @@ def main():
         cpu = dict(value=done / el, unit="doc pairs/s", cores=1, kind="oracle",
                    sample=f"first {done} pairs of the {corpus.n_pairs}-pair batch, single thread, {el:.1f} s")
         log(f"[bench] cpu oracle: {cpu}")
+        # all host cores: the same per-pair oracle over worker threads (multi-threaded miner)
+        threads = len(os.sched_getaffinity(0))
+        nsub = min(corpus.n_pairs, max(threads * 8, int(cpu["value"] * threads * args.cpu_seconds * 0.5)))
+        sub = corpus.slice(0, nsub)
+        tc0 = time.perf_counter()
+        O.mine_threads(OL, sub, w, gap, tau, threads)
+        el = time.perf_counter() - tc0
+        cpu_mt = dict(value=nsub / el, unit="doc pairs/s", cores=threads, kind="oracle_threads",
+                      sample=f"first {nsub} pairs of the batch, {threads} threads, {el:.1f} s")
+        log(f"[bench] cpu oracle, all cores: {cpu_mt}")
 
     serve = None
     if args.serve_seconds > 0:
@@ -323,6 +333,7 @@ def main():
         "plain_per_pair": plain,
         "served": serve,
         "cpu_baseline": cpu,
+        "cpu_baseline_all_cores": cpu_mt,
     }
     print(json.dumps(line), flush=True)
 

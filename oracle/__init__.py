@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-CFLAGS = ["-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
+CFLAGS = ["-O2", "-std=gnu99", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-pthread"]
 
 
 def build(force: bool = True, extra=(), out: str | None = None) -> str:
@@ -60,6 +60,11 @@ class Oracle:
         lib.oracle_emit.argtypes = [C.POINTER(C.c_float), C.c_int32, C.c_int32, C.c_char_p, C.c_int32,
                                     C.c_float, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                     C.POINTER(C.c_float), C.POINTER(C.c_int32)]
+        lib.oracle_mine_threads.argtypes = [
+            C.c_void_p, C.c_int64, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int32),
+            C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_float),
+            C.c_float, C.c_float, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+            C.POINTER(C.c_float), C.POINTER(C.c_float)]
         lib.oracle_mine.argtypes = [
             C.c_void_p, C.c_int64, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int32),
             C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_float),
@@ -155,6 +160,32 @@ class Oracle:
         if want_S:
             out["S"] = S[: corpus.cells()]
         return out
+
+
+def _mine_threads(self, lex, corpus, w, g, tau, threads):
+    """oracle_mine_threads: the per-pair oracle over `threads` worker threads."""
+    n, m = corpus.nm()
+    cap = int(np.minimum(n, m).sum()) + 1
+    P = corpus.n_pairs
+    pair_off = np.zeros(P + 1, np.int64)
+    si = np.zeros(cap, np.int32)
+    ti = np.zeros(cap, np.int32)
+    sc = np.zeros(cap, np.float32)
+    al = np.zeros(max(P, 1), np.float32)
+    w = np.ascontiguousarray(w, np.float32)
+    c = corpus
+    rc = self.lib.oracle_mine_threads(
+        lex.h, P, _p(c.src_doc_off, C.c_int64), _p(c.src_sent_off, C.c_int64), _p(_nz(c.src_tok), C.c_int32),
+        _p(c.tgt_doc_off, C.c_int64), _p(c.tgt_sent_off, C.c_int64), _p(_nz(c.tgt_tok), C.c_int32),
+        _p(w, C.c_float), np.float32(g), np.float32(tau), int(threads), _p(pair_off, C.c_int64),
+        _p(si, C.c_int32), _p(ti, C.c_int32), _p(sc, C.c_float), _p(al, C.c_float))
+    if rc:
+        raise MemoryError("oracle_mine_threads")
+    k = int(pair_off[-1])
+    return dict(pair_off=pair_off, src_idx=si[:k], tgt_idx=ti[:k], score=sc[:k], align_score=al[:P])
+
+
+Oracle.mine_threads = _mine_threads
 
 
 class OLex:

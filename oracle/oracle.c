@@ -6,8 +6,10 @@
  * Only the test suite, the smoke check and the benchmark's CPU-baseline leg
  * load it.  It shares no code, header or table with the GPU library.
  *
- * Build: gcc -O2 -std=c99 -ffp-contract=off -fno-fast-math (no FMA contraction:
- * every float product and sum below is rounded on its own).
+ * Build: gcc -O2 -std=gnu99 -ffp-contract=off -fno-fast-math -pthread (no FMA
+ * contraction: every float product and sum below is rounded on its own).  The
+ * per-pair functions are single-threaded; oracle_mine_threads at the end only
+ * hands whole pairs to worker threads.
  *
  * The method (Section 4, "Yalign and improvements"):
  *   - every source sentence of a document pair is scored against every target
@@ -372,4 +374,98 @@ int oracle_mine(const olex *L, int64_t n_pairs, const int64_t *src_doc_off, cons
     free(mv);
   }
   return 0;
+}
+
+/*
+ * Multi-threaded driver: the same per-pair computation as oracle_mine, with
+ * pairs handed to worker threads one at a time (the multi-threaded Yalign of
+ * Section 4 parallelises over article pairs the same way).  Each pair's
+ * accepted pairs go to its own slot range (prefix sums of min(n, m)); the
+ * caller-visible output is compacted afterwards exactly as oracle_mine's.
+ */
+#include <pthread.h>
+
+typedef struct {
+  const olex *L;
+  int64_t n_pairs;
+  const int64_t *sdo, *sso, *tdo, *tso;
+  const int32_t *stok, *ttok;
+  const float *w;
+  float g, tau;
+  const int64_t *slot_off;
+  int32_t *ssrc, *stgt;
+  float *sscore, *align;
+  int32_t *cnt;
+  volatile int64_t next;
+  volatile int failed;
+} mt_job;
+
+static void *mt_worker(void *arg) {
+  mt_job *J = (mt_job *)arg;
+  for (;;) {
+    const int64_t p = __sync_fetch_and_add(&J->next, 1);
+    if (p >= J->n_pairs) break;
+    const int32_t n = (int32_t)(J->sdo[p + 1] - J->sdo[p]), m = (int32_t)(J->tdo[p + 1] - J->tdo[p]);
+    const int64_t cells = (int64_t)n * m;
+    float *S = (float *)malloc(sizeof(float) * (size_t)(cells > 0 ? cells : 1));
+    char *mv = (char *)malloc((size_t)(n + m + 1));
+    int32_t nm = 0, c = 0;
+    float h = 0.0f;
+    if (!S || !mv || oracle_similarity(J->L, J->sso + J->sdo[p], J->stok, n, J->tso + J->tdo[p], J->ttok, m, J->w, S, NULL, NULL) ||
+        oracle_nw(S, n, m, J->g, NULL, mv, &nm, &h)) {
+      J->failed = 1;
+    } else {
+      const int64_t o = J->slot_off[p];
+      oracle_emit(S, n, m, mv, nm, J->tau, J->ssrc + o, J->stgt + o, J->sscore + o, &c);
+      J->cnt[p] = c;
+      J->align[p] = h;
+    }
+    free(S);
+    free(mv);
+  }
+  return NULL;
+}
+
+int oracle_mine_threads(const olex *L, int64_t n_pairs, const int64_t *src_doc_off, const int64_t *src_sent_off,
+                        const int32_t *src_tok, const int64_t *tgt_doc_off, const int64_t *tgt_sent_off,
+                        const int32_t *tgt_tok, const float w[4], float g, float tau, int n_threads, int64_t *pair_off,
+                        int32_t *src_idx, int32_t *tgt_idx, float *score, float *align_score) {
+  if (n_threads < 1) n_threads = 1;
+  int64_t *slot_off = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_pairs + 1));
+  int32_t *cnt = (int32_t *)calloc((size_t)(n_pairs > 0 ? n_pairs : 1), sizeof(int32_t));
+  if (!slot_off || !cnt) return -1;
+  slot_off[0] = 0;
+  for (int64_t p = 0; p < n_pairs; p++) {
+    const int64_t n = src_doc_off[p + 1] - src_doc_off[p], m = tgt_doc_off[p + 1] - tgt_doc_off[p];
+    slot_off[p + 1] = slot_off[p] + (n < m ? n : m);
+  }
+  const int64_t cap = slot_off[n_pairs] > 0 ? slot_off[n_pairs] : 1;
+  int32_t *ssrc = (int32_t *)malloc(sizeof(int32_t) * (size_t)cap);
+  int32_t *stgt = (int32_t *)malloc(sizeof(int32_t) * (size_t)cap);
+  float *sscore = (float *)malloc(sizeof(float) * (size_t)cap);
+  if (!ssrc || !stgt || !sscore) return -1;
+  mt_job J = {L, n_pairs, src_doc_off, src_sent_off, tgt_doc_off, tgt_sent_off, src_tok, tgt_tok, w, g, tau,
+              slot_off, ssrc, stgt, sscore, align_score, cnt, 0, 0};
+  pthread_t *th = (pthread_t *)malloc(sizeof(pthread_t) * (size_t)n_threads);
+  for (int t = 0; t < n_threads; t++) pthread_create(&th[t], NULL, mt_worker, &J);
+  for (int t = 0; t < n_threads; t++) pthread_join(th[t], NULL);
+  free(th);
+  int64_t out = 0;
+  pair_off[0] = 0;
+  for (int64_t p = 0; p < n_pairs; p++) {
+    for (int32_t k = 0; k < cnt[p]; k++) {
+      src_idx[out] = ssrc[slot_off[p] + k];
+      tgt_idx[out] = stgt[slot_off[p] + k];
+      score[out] = sscore[slot_off[p] + k];
+      out++;
+    }
+    pair_off[p + 1] = out;
+  }
+  const int failed = J.failed;
+  free(slot_off);
+  free(cnt);
+  free(ssrc);
+  free(stgt);
+  free(sscore);
+  return failed ? -1 : 0;
 }

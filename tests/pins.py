@@ -418,3 +418,63 @@ ALL = [
     check_nw_bruteforce, check_tie_rule_dyadic, check_lcs, check_constant_closed_form,
     check_threshold_and_edges, check_invariants,
 ]
+
+
+# ------------------------------------------------------------ A* (monotone)
+def astar_monotone(S, g):
+    """Best-first (A*) search for the best monotone alignment path.
+
+    Section 4 notes that A* gives the NW result only when paths may not go up
+    or left; this search walks the same DAG (moves D, U, L only).  Scores are
+    turned into non-negative step costs that do not depend on path length:
+    every path makes n + m units of progress (D counts 2, U and L count 1),
+    and score = g(n+m) + sum over D of (S - 2g).  With K = (smax - 2g)/2,
+    cost(D) = 2K - (S - 2g) >= 0 and cost(U) = cost(L) = K give
+    cost = K(n+m) - (score - g(n+m)), so the cheapest path is the best one.
+    Heuristic: K per unit of remaining progress minus the most a diagonal step
+    could save, which never overestimates.  Exact in dyadic arithmetic.
+    """
+    import heapq
+    S = np.asarray(S, dtype=np.float64)
+    n, m = S.shape
+    g = float(g)
+    smax = float(S.max()) if S.size else 0.0
+    K = max((smax - 2 * g) / 2.0, 0.0)
+    gain = max(smax - 2 * g, 0.0)
+
+    def h(i, j):
+        rem_d = min(n - i, m - j)
+        return K * ((n - i) + (m - j)) - rem_d * gain
+
+    best = {(0, 0): 0.0}
+    pq = [(h(0, 0), 0.0, 0, 0)]
+    while pq:
+        f, c, i, j = heapq.heappop(pq)
+        if c > best.get((i, j), float("inf")):
+            continue
+        if (i, j) == (n, m):
+            return g * (n + m) + (K * (n + m) - c)
+        for di, dj in ((1, 1), (1, 0), (0, 1)):
+            a, b = i + di, j + dj
+            if a > n or b > m:
+                continue
+            step = 2 * K - (S[i, j] - 2 * g) if (di, dj) == (1, 1) else K
+            nc = c + step
+            if nc < best.get((a, b), float("inf")):
+                best[(a, b)] = nc
+                heapq.heappush(pq, (nc + h(a, b), nc, a, b))
+    raise AssertionError("no path")
+
+
+def check_astar_agrees(O, n_cases=60, seed=23):
+    r = rng(seed)
+    for case in range(n_cases):
+        n, m = int(r.integers(0, 14)), int(r.integers(0, 14))
+        S = (r.integers(0, 17, (n, m)) / 16.0).astype(np.float32)
+        g = F32(-0.0625 * int(r.integers(0, 9)))
+        h, _, _ = O.nw(S, g)
+        a = astar_monotone(S, g)
+        assert float(h) == a, (case, n, m, float(g), float(h), a)
+
+
+ALL.append(check_astar_agrees)
