@@ -213,6 +213,31 @@ ym_status ym_nw_align(ym_ctx *ctx, const float *S, const int32_t *n, const int32
                       float gap, float threshold, float *align_score, char *moves, int32_t *n_moves,
                       ym_result **out);
 
+/* -------------------------------------------------- tuning and bidirectional */
+
+/* Parameter sweep for the tuned miner (Section 4: penalty and threshold can
+ * be adjusted, and this work adds a tuning algorithm for them; Section 5:
+ * the NWT variant).  Scores are computed once per chunk and reused for every
+ * gap in gaps[0..n_gaps); each gap reruns only the NW kernel, and every
+ * threshold in taus[0..n_taus) is applied while counting.  For the reference
+ * pairs given as CSR per document pair (truth_off [n_pairs+1], sentence index
+ * pairs truth_src / truth_tgt), n_mined[g * n_taus + t] receives the number
+ * of accepted pairs and n_correct[...] how many of them are reference pairs;
+ * precision, recall and F1 follow (recall denominator: truth_off[n_pairs]). */
+ym_status ym_tune(ym_ctx *ctx, const ym_lexicon *lex, const ym_batch *batch, const float w[4], const float *gaps,
+                  int32_t n_gaps, const float *taus, int32_t n_taus, const int64_t *truth_off,
+                  const int32_t *truth_src, const int32_t *truth_tgt, int64_t *n_mined, int64_t *n_correct);
+
+/* Bidirectional mining (Section 5: a second classifier trained in the other
+ * direction, results joined without duplicates).  Mines the batch forward
+ * with (lex_fwd, fwd) and with source and target swapped with (lex_rev, rev),
+ * maps the reverse pairs back to (source index, target index), and returns
+ * per document pair the union ordered by (source, target) index.  A pair
+ * found both ways carries its forward score; align_score is the forward
+ * H[n][m]. */
+ym_status ym_mine_bidirectional(ym_ctx *ctx, const ym_lexicon *lex_fwd, const ym_lexicon *lex_rev,
+                                const ym_batch *batch, const ym_params *fwd, const ym_params *rev, ym_result **out);
+
 /* ------------------------------------------------------------ kernel timing */
 
 /* Record HIP events around every kernel the context launches (on the stream

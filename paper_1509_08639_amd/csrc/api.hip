@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
@@ -333,6 +334,178 @@ ym_status ym_mine_device(ym_ctx *c, const ym_lexicon *L, const ym_device_batch *
       return s;
   }
   return YM_OK;
+}
+
+// A device buffer owned by one call (freed on every return path).
+struct CallBuf : DevBuf {
+  CallBuf() = default;
+  CallBuf(const CallBuf &) = delete;
+  CallBuf &operator=(const CallBuf &) = delete;
+  ~CallBuf() { release(); }
+};
+
+ym_status ym_tune(ym_ctx *c, const ym_lexicon *L, const ym_batch *b, const float w[4], const float *gaps, int32_t n_gaps,
+                  const float *taus, int32_t n_taus, const int64_t *truth_off, const int32_t *truth_src,
+                  const int32_t *truth_tgt, int64_t *n_mined, int64_t *n_correct) {
+  if (!c || !L || !w || !gaps || !taus || !truth_off || !n_mined || !n_correct) return fail(YM_EINVAL, "NULL argument");
+  if (n_gaps < 1 || n_taus < 1) return fail(YM_EINVAL, "need at least one gap and one threshold");
+  ym_params prm;
+  std::memcpy(prm.w, w, sizeof prm.w);
+  prm.gap = 0.0f;
+  prm.threshold = 0.0f;
+  ym_status s;
+  if ((s = check_params(&prm))) return s;
+  for (int k = 0; k < n_gaps; k++)
+    if (!std::isfinite(gaps[k])) return fail(YM_EINVAL, "gap %d is not finite", k);
+  for (int k = 0; k < n_taus; k++)
+    if (!std::isfinite(taus[k])) return fail(YM_EINVAL, "threshold %d is not finite", k);
+  HostBatchInfo info;
+  if ((s = check_host_batch(b, info))) return s;
+  const int64_t P = b->n_pairs;
+  if ((s = check_doc_off(truth_off, P, "truth_off"))) return s;
+  const int64_t nt = truth_off[P];
+  if (nt > 0 && (!truth_src || !truth_tgt)) return fail(YM_EINVAL, "NULL truth arrays");
+  hipSetDevice(c->device);
+  std::lock_guard<std::mutex> lk(c->mu);
+  DevBatch d;
+  if ((s = upload_batch(c, b, info, d))) return s;
+  ym_device_out o;
+  if ((s = alloc_outputs(c, P, capacity_of(b->src_doc_off, b->tgt_doc_off, P), o))) return s;
+  if ((s = ensure_table(c, &prm, c->stream))) return s;
+  // device copies: reference pairs, thresholds, counters
+  CallBuf aux;
+  const size_t s1 = a256((size_t)(P + 1) * 8), s2 = a256((size_t)std::max<int64_t>(nt, 1) * 4), s3 = a256((size_t)n_taus * 4),
+               s4 = a256((size_t)n_gaps * n_taus * 8);
+  if ((s = aux.reserve(s1 + 2 * s2 + s3 + 2 * s4))) return s;
+  char *x = (char *)aux.ptr;
+  int64_t *d_toff = (int64_t *)x;
+  int32_t *d_tsrc = (int32_t *)(x + s1), *d_ttgt = (int32_t *)(x + s1 + s2);
+  float *d_taus = (float *)(x + s1 + 2 * s2);
+  unsigned long long *d_mined = (unsigned long long *)(x + s1 + 2 * s2 + s3), *d_corr = d_mined + (s4 / 8);
+  hipError_t e = hipMemcpyAsync(d_toff, truth_off, (size_t)(P + 1) * 8, hipMemcpyHostToDevice, c->stream);
+  if (!e && nt) e = hipMemcpyAsync(d_tsrc, truth_src, (size_t)nt * 4, hipMemcpyHostToDevice, c->stream);
+  if (!e && nt) e = hipMemcpyAsync(d_ttgt, truth_tgt, (size_t)nt * 4, hipMemcpyHostToDevice, c->stream);
+  if (!e) e = hipMemcpyAsync(d_taus, taus, (size_t)n_taus * 4, hipMemcpyHostToDevice, c->stream);
+  if (!e) e = hipMemsetAsync(d_mined, 0, 2 * s4, c->stream);
+  if (e) return hip_fail(e, "tune upload");
+  std::vector<std::pair<int64_t, int64_t>> chunks;
+  const size_t head = trans_bytes(info.n_src_tok);
+  const size_t full = full_workspace(b->src_doc_off, b->tgt_doc_off, P, info.n_src_tok);
+  const size_t wsb = std::max(std::min(full, c->arena_limit + head), min_workspace(b->src_doc_off, b->tgt_doc_off, P, info.n_src_tok));
+  if ((s = plan_chunks(b->src_doc_off, b->tgt_doc_off, P, wsb - head, chunks))) return s;
+  std::vector<Chunk> lay(chunks.size());
+  size_t need = 256;
+  for (size_t k = 0; k < chunks.size(); k++) {
+    lay[k].layout(b->src_doc_off, b->tgt_doc_off, chunks[k].first, chunks[k].second);
+    need = std::max(need, lay[k].bytes);
+  }
+  if ((s = c->ws.reserve(head + need))) return s;
+  if ((s = translate_batch(c, L, d, (char *)c->ws.ptr, c->stream))) return s;
+  char *ws = (char *)c->ws.ptr + head;
+  for (size_t k = 0; k < chunks.size(); k++) {
+    const Chunk &ch = lay[k];
+    DebugOut sim;
+    sim.sim_only = true;  // scores once per chunk, kept in the workspace
+    if ((s = run_chunk(c, L, d, &prm, b->src_doc_off, b->tgt_doc_off, ch, ws, o, c->stream, &sim))) return s;
+    for (int gi = 0; gi < n_gaps; gi++) {
+      DebugOut nw;
+      nw.reuse_S = true;
+      ym_params pg = prm;
+      pg.gap = gaps[gi];
+      pg.threshold = -INFINITY;  // keep every diagonal move; thresholds are applied while counting
+      if ((s = run_chunk(c, L, d, &pg, b->src_doc_off, b->tgt_doc_off, ch, ws, o, c->stream, &nw))) return s;
+      e = launch_tune_count((const PairDesc *)(ws + ch.off_descs), ch.np, ch.p0, (const int32_t *)(ws + ch.off_counts),
+                            (const int32_t *)(ws + ch.off_ssrc), (const int32_t *)(ws + ch.off_stgt),
+                            (const float *)(ws + ch.off_sscore), d_toff, d_tsrc, d_ttgt, d_taus, n_taus,
+                            d_mined + (size_t)gi * n_taus, d_corr + (size_t)gi * n_taus, c->stream);
+      if (e) return hip_fail(e, "tune count");
+    }
+  }
+  std::vector<unsigned long long> hm((size_t)n_gaps * n_taus), hc((size_t)n_gaps * n_taus);
+  e = hipMemcpyAsync(hm.data(), d_mined, hm.size() * 8, hipMemcpyDeviceToHost, c->stream);
+  if (!e) e = hipMemcpyAsync(hc.data(), d_corr, hc.size() * 8, hipMemcpyDeviceToHost, c->stream);
+  if (!e) e = hipStreamSynchronize(c->stream);
+  if (e) return hip_fail(e, "tune download");
+  for (size_t k = 0; k < hm.size(); k++) {
+    n_mined[k] = (int64_t)hm[k];
+    n_correct[k] = (int64_t)hc[k];
+  }
+  return YM_OK;
+}
+
+ym_status ym_mine_bidirectional(ym_ctx *c, const ym_lexicon *Lf, const ym_lexicon *Lr, const ym_batch *b,
+                                const ym_params *pf, const ym_params *pr, ym_result **out) {
+  if (!out) return fail(YM_EINVAL, "NULL out");
+  *out = nullptr;
+  if (!c || !Lf || !Lr) return fail(YM_EINVAL, "NULL context or lexicon");
+  ym_status s;
+  if ((s = check_params(pf)) || (s = check_params(pr))) return s;
+  HostBatchInfo info;
+  if ((s = check_host_batch(b, info))) return s;
+  const int64_t P = b->n_pairs;
+  hipSetDevice(c->device);
+  std::lock_guard<std::mutex> lk(c->mu);
+  DevBatch d;
+  if ((s = upload_batch(c, b, info, d))) return s;
+  DevBatch dr = d;  // the same documents with the roles swapped
+  std::swap(dr.src_sent_off, dr.tgt_sent_off);
+  std::swap(dr.src_tok, dr.tgt_tok);
+  std::swap(dr.n_src_sent, dr.n_tgt_sent);
+  std::swap(dr.n_src_tok, dr.n_tgt_tok);
+  const int64_t cap = capacity_of(b->src_doc_off, b->tgt_doc_off, P);
+  // forward and reverse results (device), then the union in the context's output buffers
+  CallBuf two;
+  const size_t q1 = a256((size_t)(P + 1) * 8), q2 = a256((size_t)std::max<int64_t>(P, 1) * 4),
+               q3 = a256((size_t)std::max<int64_t>(cap, 1) * 4);
+  const size_t per = q1 + q2 + 3 * q3;
+  if ((s = two.reserve(2 * per + q2))) return s;
+  ym_device_out of, orv;
+  for (int k = 0; k < 2; k++) {
+    char *x = (char *)two.ptr + k * per;
+    ym_device_out &o = k ? orv : of;
+    o.pair_off = (int64_t *)x;
+    o.align_score = (float *)(x + q1);
+    o.src_idx = (int32_t *)(x + q1 + q2);
+    o.tgt_idx = (int32_t *)(x + q1 + q2 + q3);
+    o.score = (float *)(x + q1 + q2 + 2 * q3);
+  }
+  int32_t *counts = (int32_t *)((char *)two.ptr + 2 * per);
+  ym_device_out o;
+  if ((s = alloc_outputs(c, P, 2 * cap, o))) return s;
+  const size_t head = trans_bytes(std::max(info.n_src_tok, info.n_tgt_tok));
+  for (int dir = 0; dir < 2; dir++) {
+    const int64_t *sdo = dir ? b->tgt_doc_off : b->src_doc_off, *tdo = dir ? b->src_doc_off : b->tgt_doc_off;
+    DevBatch &db = dir ? dr : d;
+    const ym_lexicon *L = dir ? Lr : Lf;
+    const ym_params *prm = dir ? pr : pf;
+    const ym_device_out &od = dir ? orv : of;
+    if ((s = ensure_table(c, prm, c->stream))) return s;
+    std::vector<std::pair<int64_t, int64_t>> chunks;
+    const size_t full = full_workspace(sdo, tdo, P, 0);
+    const size_t wsb = std::max(std::min(full, c->arena_limit), min_workspace(sdo, tdo, P, 0));
+    if ((s = plan_chunks(sdo, tdo, P, wsb, chunks))) return s;
+    std::vector<Chunk> lay(chunks.size());
+    size_t need = 256;
+    for (size_t k = 0; k < chunks.size(); k++) {
+      lay[k].layout(sdo, tdo, chunks[k].first, chunks[k].second);
+      need = std::max(need, lay[k].bytes);
+    }
+    if ((s = c->ws.reserve(head + need))) return s;
+    if ((s = translate_batch(c, L, db, (char *)c->ws.ptr, c->stream))) return s;
+    for (size_t k = 0; k < chunks.size(); k++)
+      if ((s = run_chunk(c, L, db, prm, sdo, tdo, lay[k], (char *)c->ws.ptr + head, od, c->stream, nullptr))) return s;
+  }
+  hipError_t e = launch_merge_bi(P, of.pair_off, of.src_idx, of.tgt_idx, of.score, orv.pair_off, orv.src_idx, orv.tgt_idx,
+                                 orv.score, counts, nullptr, nullptr, nullptr, nullptr, c->stream);
+  if (!e) e = launch_scan(counts, P, o.pair_off, 1, c->stream);
+  if (!e) e = launch_merge_bi(P, of.pair_off, of.src_idx, of.tgt_idx, of.score, orv.pair_off, orv.src_idx, orv.tgt_idx,
+                              orv.score, counts, o.pair_off, o.src_idx, o.tgt_idx, o.score, c->stream);
+  if (!e && P) e = hipMemcpyAsync(o.align_score, of.align_score, (size_t)P * 4, hipMemcpyDeviceToDevice, c->stream);
+  if (e) return hip_fail(e, "bidirectional merge");
+  if (P == 0 && (e = hipMemsetAsync(o.pair_off, 0, 8, c->stream))) return hip_fail(e, "memset");
+  s = download_result(c, P, o, out);
+  hipStreamSynchronize(c->stream);
+  return s;
 }
 
 ym_status ym_nw_align(ym_ctx *c, const float *S, const int32_t *n, const int32_t *m, int64_t n_pairs, float gap,

@@ -1077,6 +1077,87 @@ __global__ __launch_bounds__(64) void compact_kernel(const PairDesc *descs, int6
   }
 }
 
+// ---------------------------------------------------- tuning (NWT) counts
+// For every accepted-before-threshold pair of every document pair (NW run
+// with tau = -inf), and every threshold taus[t]: is it kept (score >= tau),
+// and is it a reference pair?  Wave-level ballots feed two counters per t.
+__global__ __launch_bounds__(64) void tune_count_kernel(const PairDesc *descs, int64_t n_pairs, int64_t pair_base,
+                                                        const int32_t *counts, const int32_t *ssrc, const int32_t *stgt,
+                                                        const float *sscore, const int64_t *truth_off,
+                                                        const int32_t *truth_src, const int32_t *truth_tgt,
+                                                        const float *taus, int n_taus,
+                                                        unsigned long long *n_mined, unsigned long long *n_correct) {
+  const int64_t p = blockIdx.x;
+  if (p >= n_pairs) return;
+  const int lane = threadIdx.x;
+  const int c = counts[p];
+  const int64_t base = descs[p].out_off;
+  const int64_t t0 = truth_off[pair_base + p], t1 = truth_off[pair_base + p + 1];
+  for (int k0 = 0; k0 < c; k0 += 64) {
+    const int k = k0 + lane;
+    const bool valid = k < c;
+    int si = -1, ti = -1;
+    float sv = 0.0f;
+    bool hit = false;
+    if (valid) {
+      si = ssrc[base + k];
+      ti = stgt[base + k];
+      sv = sscore[base + k];
+      for (int64_t e = t0; e < t1 && !hit; e++) hit = truth_src[e] == si && truth_tgt[e] == ti;
+    }
+    for (int t = 0; t < n_taus; t++) {
+      const bool keep = valid && sv >= taus[t];
+      const uint64_t bm = __ballot(keep), bc = __ballot(keep && hit);
+      if (lane == 0) {
+        if (bm) atomicAdd(&n_mined[t], (unsigned long long)__popcll(bm));
+        if (bc) atomicAdd(&n_correct[t], (unsigned long long)__popcll(bc));
+      }
+    }
+  }
+}
+
+// ---------------------------------------------- bidirectional union (BI)
+// Pair p's forward result (i, j) and reverse result, mined with source and
+// target swapped and mapped back to (i, j) = (its target index, its source
+// index), are both strictly increasing in i and j; their union, without
+// duplicates and ordered by (i, j), is merged by one lane per pair.  The
+// forward score is kept for pairs found both ways.  Pass 1 counts, pass 2
+// writes at the scanned offsets.
+__global__ __launch_bounds__(64) void merge_bi_kernel(int64_t n_pairs, const int64_t *po_f, const int32_t *sf,
+                                                      const int32_t *tf, const float *scf, const int64_t *po_r,
+                                                      const int32_t *sr, const int32_t *tr, const float *scr,
+                                                      int32_t *counts, const int64_t *po_out, int32_t *osrc,
+                                                      int32_t *otgt, float *osc) {
+  const int64_t p = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  if (p >= n_pairs) return;
+  int64_t a = po_f[p], ae = po_f[p + 1], b = po_r[p], be = po_r[p + 1];
+  int64_t o = po_out ? po_out[p] : 0;
+  int k = 0;
+  while (a < ae || b < be) {
+    int i, j;
+    float v;
+    if (b >= be || (a < ae && (sf[a] < tr[b] || (sf[a] == tr[b] && tf[a] <= sr[b])))) {
+      i = sf[a];
+      j = tf[a];
+      v = scf[a];
+      if (b < be && tr[b] == i && sr[b] == j) b++;
+      a++;
+    } else {
+      i = tr[b];
+      j = sr[b];
+      v = scr[b];
+      b++;
+    }
+    if (po_out) {
+      osrc[o + k] = i;
+      otgt[o + k] = j;
+      osc[o + k] = v;
+    }
+    k++;
+  }
+  if (!po_out) counts[p] = k;
+}
+
 __global__ void fill_i32_kernel(int32_t *p, int32_t v, int64_t n) {
   const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (k < n) p[k] = v;
@@ -1136,6 +1217,25 @@ hipError_t launch_relayout(const PairDesc *descs, int64_t n_pairs, const float *
                            hipStream_t st) {
   if (n_pairs <= 0) return hipSuccess;
   hipLaunchKernelGGL(relayout_kernel, dim3(64, (unsigned)n_pairs), dim3(256), 0, st, descs, n_pairs, src, dst, to_diag);
+  return hipGetLastError();
+}
+
+hipError_t launch_tune_count(const PairDesc *descs, int64_t n_pairs, int64_t pair_base, const int32_t *counts,
+                             const int32_t *ssrc, const int32_t *stgt, const float *sscore, const int64_t *truth_off,
+                             const int32_t *truth_src, const int32_t *truth_tgt, const float *taus, int n_taus,
+                             unsigned long long *n_mined, unsigned long long *n_correct, hipStream_t st) {
+  if (n_pairs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(tune_count_kernel, dim3((unsigned)n_pairs), dim3(64), 0, st, descs, n_pairs, pair_base, counts,
+                     ssrc, stgt, sscore, truth_off, truth_src, truth_tgt, taus, n_taus, n_mined, n_correct);
+  return hipGetLastError();
+}
+
+hipError_t launch_merge_bi(int64_t n_pairs, const int64_t *po_f, const int32_t *sf, const int32_t *tf, const float *scf,
+                           const int64_t *po_r, const int32_t *sr, const int32_t *tr, const float *scr, int32_t *counts,
+                           const int64_t *po_out, int32_t *osrc, int32_t *otgt, float *osc, hipStream_t st) {
+  if (n_pairs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(merge_bi_kernel, dim3((unsigned)((n_pairs + 63) / 64)), dim3(64), 0, st, n_pairs, po_f, sf, tf, scf,
+                     po_r, sr, tr, scr, counts, po_out, osrc, otgt, osc);
   return hipGetLastError();
 }
 

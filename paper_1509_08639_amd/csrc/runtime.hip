@@ -523,7 +523,9 @@ ym_status run_chunk(ym_ctx *c, const ym_lexicon *L, const DevBatch &b, const ym_
 
   const PairDesc *descs = (const PairDesc *)(ws + ch.off_descs);
   float *S = (float *)(ws + ch.off_S);  // strip-diagonal layout
-  if (dbg && dbg->S_rowmajor_in) {
+  if (dbg && dbg->reuse_S) {
+    // scores computed by an earlier run of this chunk
+  } else if (dbg && dbg->S_rowmajor_in) {
     if ((e = launch_relayout(descs, ch.np, dbg->S_rowmajor_in, S, 1, st)) != hipSuccess) return hip_fail(e, "relayout");
   } else {
     SimArgs a;

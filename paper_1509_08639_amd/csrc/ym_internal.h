@@ -107,6 +107,13 @@ hipError_t launch_compact(const PairDesc *descs, int64_t n_pairs, const int32_t 
                           int32_t *out_tgt, float *out_score, hipStream_t st);
 hipError_t launch_relayout(const PairDesc *descs, int64_t n_pairs, const float *src, float *dst, int to_diag,
                            hipStream_t st);
+hipError_t launch_tune_count(const PairDesc *descs, int64_t n_pairs, int64_t pair_base, const int32_t *counts,
+                             const int32_t *ssrc, const int32_t *stgt, const float *sscore, const int64_t *truth_off,
+                             const int32_t *truth_src, const int32_t *truth_tgt, const float *taus, int n_taus,
+                             unsigned long long *n_mined, unsigned long long *n_correct, hipStream_t st);
+hipError_t launch_merge_bi(int64_t n_pairs, const int64_t *po_f, const int32_t *sf, const int32_t *tf, const float *scf,
+                           const int64_t *po_r, const int32_t *sr, const int32_t *tr, const float *scr, int32_t *counts,
+                           const int64_t *po_out, int32_t *osrc, int32_t *otgt, float *osc, hipStream_t st);
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st);
 
 }  // namespace ym

@@ -42,6 +42,7 @@ struct DebugOut {
   float *S_rowmajor_out = nullptr;       // if set: the chunk's scores, row-major, go here (device)
   const float *S_rowmajor_in = nullptr;  // if set: use these row-major scores, skip the similarity kernel
   bool sim_only = false;                 // stop after the similarity kernel
+  bool reuse_S = false;                  // the workspace already holds this chunk's scores
   int32_t *ms = nullptr, *mt = nullptr;
   char *moves_dev = nullptr; // device buffer for paths
   int64_t moves_base = 0;    // offset of this chunk's first pair in moves_dev

@@ -29,7 +29,7 @@ EXPORTS = [
     "ym_create", "ym_destroy", "ym_last_error", "ym_version", "ym_lexicon_load", "ym_lexicon_free",
     "ym_lexicon_stats", "ym_mine", "ym_result_free", "ym_mine_per_pair", "ym_mine_device_capacity",
     "ym_mine_device_workspace", "ym_mine_device_workspace_min", "ym_mine_device", "ym_similarity",
-    "ym_nw_align", "ym_profile_enable", "ym_profile_read", "ym_server_start", "ym_submit", "ym_poll", "ym_server_next_done", "ym_cancel",
+    "ym_nw_align", "ym_tune", "ym_mine_bidirectional", "ym_profile_enable", "ym_profile_read", "ym_server_start", "ym_submit", "ym_poll", "ym_server_next_done", "ym_cancel",
     "ym_server_stop",
     "ym_server_stats",
 ]
@@ -107,6 +107,8 @@ def lib():
     L.ym_similarity.argtypes = [vp, vp, P(Batch), P(Params), P(f32), P(i32), P(i32)]
     L.ym_nw_align.argtypes = [vp, P(f32), P(i32), P(i32), i64, f32, f32, P(f32), C.c_char_p, P(i32),
                               P(P(Result))]
+    L.ym_tune.argtypes = [vp, vp, P(Batch), P(f32), P(f32), i32, P(f32), i32, P(i64), P(i32), P(i32), P(i64), P(i64)]
+    L.ym_mine_bidirectional.argtypes = [vp, vp, vp, P(Batch), P(Params), P(Params), P(P(Result))]
     L.ym_profile_enable.argtypes = [vp, C.c_int]
     L.ym_profile_read.argtypes = [vp, P(C.c_double), P(i64)]
     L.ym_server_start.argtypes = [vp, vp, P(Params), P(ServerOpts), P(vp)]
@@ -298,6 +300,31 @@ def nw_align(ctx: Context, mats, gap, threshold):
         moves.append(raw[base:base + int(nmv[k])].decode())
         base += int(n[k]) + int(m[k])
     return align[:P_], moves, _result_to_numpy(rp)
+
+
+def tune(ctx: Context, lex: Lexicon, corpus, w, gaps, taus, truth_off, truth_src, truth_tgt):
+    """ym_tune: (n_mined, n_correct) arrays of shape [len(gaps), len(taus)]."""
+    hb = _HostBatch(corpus)
+    w = _c(w, np.float32)
+    g = _c(gaps, np.float32)
+    t = _c(taus, np.float32)
+    to, ts, tt = _c(truth_off, np.int64), _c(truth_src, np.int32), _c(truth_tgt, np.int32)
+    nm = np.zeros(len(gaps) * len(taus), np.int64)
+    nc = np.zeros(len(gaps) * len(taus), np.int64)
+    _check(lib().ym_tune(ctx.h, lex.h, C.byref(hb.b), _ptr(w, f32), _ptr(g, f32), len(gaps), _ptr(t, f32), len(taus),
+                         _ptr(to, i64), _ptr(ts, i32), _ptr(tt, i32), _ptr(nm, i64), _ptr(nc, i64)))
+    return nm.reshape(len(gaps), len(taus)), nc.reshape(len(gaps), len(taus))
+
+
+def mine_bidirectional(ctx: Context, lex_fwd: Lexicon, lex_rev: Lexicon, corpus, w_fwd, w_rev, gap, threshold) -> dict:
+    """ym_mine_bidirectional: union of forward and reverse mining per pair."""
+    hb = _HostBatch(corpus)
+    pf = params(w_fwd, gap, threshold)
+    pr = params(w_rev, gap, threshold)
+    rp = P(Result)()
+    _check(lib().ym_mine_bidirectional(ctx.h, lex_fwd.h, lex_rev.h, C.byref(hb.b), C.byref(pf), C.byref(pr),
+                                       C.byref(rp)))
+    return _result_to_numpy(rp)
 
 
 class DeviceMiner:
