@@ -226,9 +226,31 @@ __device__ __forceinline__ int64_t score_pos_fast(int i, int c, int n, int m) {
   return score_pos(i, c, n, m);
 }
 
+// LDS hash entry of the lanes kernel: key and its dense local id side by
+// side, so a lookup is one 8-byte read.
+__device__ __forceinline__ int u2_insert(int2 *ent, int32_t x) {
+  uint32_t h = hash32(x) >> (32 - kLogUcap);
+  for (;;) {  // at most kTcap distinct keys in kUcap slots
+    const int prev = atomicCAS(&ent[h].x, kEmpty, x);
+    if (prev == kEmpty || prev == x) return (int)h;
+    h = (h + 1) & (kUcap - 1);
+  }
+}
+
+// local id of target id x in the chunk, 0 if x is not one of its ids
+__device__ __forceinline__ int u2_lid(const int2 *ent, int32_t x) {
+  if (x < 0) return 0;
+  uint32_t h = hash32(x) >> (32 - kLogUcap);
+  int2 e = ent[h];
+  while (e.x != x && e.x != kEmpty) {
+    h = (h + 1) & (kUcap - 1);
+    e = ent[h];
+  }
+  return e.x == x ? e.y : 0;
+}
+
 __global__ __launch_bounds__(kSimThreads, 4) void sim_kernel(SimArgs a) {
-  __shared__ int32_t ukey[kUcap];
-  __shared__ uint16_t ulid[kUcap];
+  __shared__ int2 uent[kUcap];
   __shared__ __align__(16) uint16_t tdoc[kTdocCap];
   __shared__ uint16_t toff[kJcap];        // start of sentence jj in the padded staging
   __shared__ uint16_t toff_o[kJcap + 1];  // start of sentence jj in the chunk's token range
@@ -237,7 +259,8 @@ __global__ __launch_bounds__(kSimThreads, 4) void sim_kernel(SimArgs a) {
   __shared__ int sh_scan[kSimWaves];
   __shared__ int sh_j1;
 
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
   uint32_t *Mw = Mw_all[wv];
   const char *Mb = reinterpret_cast<const char *>(Mw);
 
@@ -262,7 +285,7 @@ __global__ __launch_bounds__(kSimThreads, 4) void sim_kernel(SimArgs a) {
         }
         sh_j1 = lo;
       }
-      for (int s = tid; s < kUcap; s += kSimThreads) ukey[s] = kEmpty;
+      for (int s = tid; s < kUcap; s += kSimThreads) uent[s] = make_int2(kEmpty, 0);
       __syncthreads();
       const int j1 = sh_j1;
       const int nj = j1 - j0;
@@ -293,26 +316,29 @@ __global__ __launch_bounds__(kSimThreads, 4) void sim_kernel(SimArgs a) {
             hi = mid - 1;
         }
         const int32_t x = a.tgt_tok[tbase + p];
-        tdoc[toff[lo] + (p - toff_o[lo])] = x < 0 ? (uint16_t)0xFFFF : (uint16_t)u_insert(ukey, x);
+        tdoc[toff[lo] + (p - toff_o[lo])] = x < 0 ? (uint16_t)0xFFFF : (uint16_t)u2_insert(uent, x);
       }
       __syncthreads();
       // dense local ids 1..nlid-1 in slot order (0 = "no such id", its word stays 0)
       constexpr int kSpt = kUcap / kSimThreads;
       int cnt = 0;
 #pragma unroll
-      for (int k = 0; k < kSpt; k++) cnt += (ukey[tid * kSpt + k] != kEmpty);
+      for (int k = 0; k < kSpt; k++) cnt += (uent[tid * kSpt + k].x != kEmpty);
       int total;
       int r = block_excl_sum256(cnt, sh_scan, &total);
 #pragma unroll
       for (int k = 0; k < kSpt; k++) {
         const int s = tid * kSpt + k;
-        if (ukey[s] != kEmpty) ulid[s] = (uint16_t)(1 + r++);
+        if (uent[s].x != kEmpty) uent[s].y = 1 + r++;
       }
       const int nlid = total + 1;
+      // every wave's mask words start at zero; each source sentence clears what it set
+      for (int k = tid; k < kSimWaves * (kTcap + 4) / 4; k += kSimThreads)
+        reinterpret_cast<uint4 *>(&Mw_all[0][0])[k] = make_uint4(0, 0, 0, 0);
       __syncthreads();
       for (int q = tid; q < npad; q += kSimThreads) {
         const uint16_t s = tdoc[q];
-        tdoc[q] = s == 0xFFFF ? (uint16_t)0 : ulid[s];
+        tdoc[q] = s == 0xFFFF ? (uint16_t)0 : (uint16_t)uent[s].y;
       }
       __syncthreads();
 
@@ -323,7 +349,7 @@ __global__ __launch_bounds__(kSimThreads, 4) void sim_kernel(SimArgs a) {
       uint32_t ad[kRegTok];
 #pragma unroll
       for (int k = 0; k < kRegTok; k++) ad[k] = k < bl ? (uint32_t)tp[k] << 2 : 0u;
-      const int maxb = wave_max(bl);
+      const int maxb = __builtin_amdgcn_readfirstlane(wave_max(bl));
       const int ng = (min(maxb, kRegTok) + 3) >> 2;
       const int nq4 = (nlid + 3) >> 2;
 
@@ -339,45 +365,126 @@ __global__ __launch_bounds__(kSimThreads, 4) void sim_kernel(SimArgs a) {
       for (int i = it.i0 + wv; i < it.i1; i += kSimWaves) {
         const int64_t sb = clamp64(soffs[i], 0, a.n_src_tok);
         const int64_t se = clamp64(soffs[i + 1], sb, a.n_src_tok);
-        const int ai = (int)min<int64_t>(se - sb, 0x7fffffff);
-        const int npass = ai <= kPosBits ? 1 : (ai + kPosBits - 1) / kPosBits;
+        const int ai = (int)min(se - sb, (int64_t)0x7fffffff);
         const int4 cur = pre;
         pre = fetch(i + kSimWaves);
         uint32_t ms_acc = 0, mt_acc = 0;
-        for (int c = 0; c < npass; c++) {
-          for (int k = lane; k < nq4; k += 64) reinterpret_cast<uint4 *>(Mw)[k] = make_uint4(0, 0, 0, 0);
-          wave_sync();
-          const int qlo = c == 0 ? 0 : kPosBits * c;
-          const int qhi = c == 0 ? ai : min(ai, kPosBits * c + kPosBits);
-          for (int q = qlo + lane; q < qhi; q += 64) {
-            const int4 t4 = (c == 0 && q < 64) ? cur : a.trans[sb + q];
-            const int rel = q - kPosBits * c;
+        if (ai <= 64) {
+          // one token per lane: its (at most four) local ids stay in registers
+          // and only those words are cleared afterwards
+          const bool far = cur.x == -2;  // more than four translations
+          int l0 = 0, l1 = 0, l2 = 0, l3 = 0;
+          if (!far) {
+            l0 = u2_lid(uent, cur.x);
+            l1 = u2_lid(uent, cur.y);
+            l2 = u2_lid(uent, cur.z);
+            l3 = u2_lid(uent, cur.w);
+          }
+          const int npass = ai <= kPosBits ? 1 : (ai + kPosBits - 1) / kPosBits;
+          for (int c = 0; c < npass; c++) {
+            const int rel = lane - kPosBits * c;
             const uint32_t bits = (c == 0 ? kHitBit : 0u) | (rel >= 0 && rel < kPosBits ? (1u << rel) : 0u);
-            scatter_token(t4, bits, ukey, ulid, Mw, a.lex.vals);
-          }
-          wave_sync();
-          uint32_t acc = 0, mt = 0;
+            if (lane < ai && bits) {
+              if (far) {
+                for (int e = 0; e < cur.z; e++) {
+                  const int l = u2_lid(uent, a.lex.vals[cur.y + e]);
+                  if (l) atomicOr(&Mw[l], bits);
+                }
+              } else {
+                if (l0) atomicOr(&Mw[l0], bits);
+                if (l1) atomicOr(&Mw[l1], bits);
+                if (l2) atomicOr(&Mw[l2], bits);
+                if (l3) atomicOr(&Mw[l3], bits);
+              }
+            }
+            wave_sync();
+            uint32_t acc = 0, mt = 0;
 #pragma unroll
-          for (int g = 0; g < kRegTok / 4; g++) {
-            if (g < ng) {
-              const uint32_t w0 = *reinterpret_cast<const uint32_t *>(Mb + ad[4 * g]);
-              const uint32_t w1 = *reinterpret_cast<const uint32_t *>(Mb + ad[4 * g + 1]);
-              const uint32_t w2 = *reinterpret_cast<const uint32_t *>(Mb + ad[4 * g + 2]);
-              const uint32_t w3 = *reinterpret_cast<const uint32_t *>(Mb + ad[4 * g + 3]);
-              mt += ((w0 >> 31) + (w1 >> 31)) + ((w2 >> 31) + (w3 >> 31));
-              acc |= (w0 | w1) | (w2 | w3);
+            for (int g = 0; g < kRegTok / 4; g++) {
+              if (g < ng) {
+                const uint32_t w0 = *reinterpret_cast<const uint32_t *>(Mb + ad[4 * g]);
+                const uint32_t w1 = *reinterpret_cast<const uint32_t *>(Mb + ad[4 * g + 1]);
+                const uint32_t w2 = *reinterpret_cast<const uint32_t *>(Mb + ad[4 * g + 2]);
+                const uint32_t w3 = *reinterpret_cast<const uint32_t *>(Mb + ad[4 * g + 3]);
+                mt += ((w0 >> 31) + (w1 >> 31)) + ((w2 >> 31) + (w3 >> 31));
+                acc |= (w0 | w1) | (w2 | w3);
+              }
             }
-          }
-          if (maxb > kRegTok) {  // sentences beyond 32 tokens: the rest straight from LDS
-            for (int k = kRegTok; k < bl; k++) {
-              const uint32_t w = Mw[tp[k]];
-              mt += w >> 31;
-              acc |= w;
+            if (maxb > kRegTok) {  // sentences beyond 32 tokens: the rest straight from LDS
+              for (int k = kRegTok; k < bl; k++) {
+                const uint32_t w = Mw[tp[k]];
+                mt += w >> 31;
+                acc |= w;
+              }
             }
+            ms_acc += __popc(acc & ~kHitBit);
+            if (c == 0) mt_acc = mt;
+            wave_sync();
+            if (lane < ai) {
+              if (far) {
+                for (int e = 0; e < cur.z; e++) {
+                  const int l = u2_lid(uent, a.lex.vals[cur.y + e]);
+                  if (l) Mw[l] = 0;
+                }
+              } else {
+                if (l0) Mw[l0] = 0;
+                if (l1) Mw[l1] = 0;
+                if (l2) Mw[l2] = 0;
+                if (l3) Mw[l3] = 0;
+              }
+            }
+            wave_sync();
           }
-          ms_acc += __popc(acc & ~kHitBit);
-          if (c == 0) mt_acc = mt;
-          wave_sync();
+        } else {
+          // long source sentence: several positions per lane, whole mask cleared per pass
+          const int npass = (ai + kPosBits - 1) / kPosBits;
+          for (int c = 0; c < npass; c++) {
+            const int qlo = c == 0 ? 0 : kPosBits * c;
+            const int qhi = c == 0 ? ai : min(ai, kPosBits * c + kPosBits);
+            for (int q = qlo + lane; q < qhi; q += 64) {
+              const int4 t4 = (c == 0 && q < 64) ? cur : a.trans[sb + q];  // cur holds position `lane`
+              const int rel = q - kPosBits * c;
+              const uint32_t bits = (c == 0 ? kHitBit : 0u) | (rel >= 0 && rel < kPosBits ? (1u << rel) : 0u);
+              if (t4.x == -2) {
+                for (int e = 0; e < t4.z; e++) {
+                  const int l = u2_lid(uent, a.lex.vals[t4.y + e]);
+                  if (l) atomicOr(&Mw[l], bits);
+                }
+              } else {
+                const int l0 = u2_lid(uent, t4.x), l1 = u2_lid(uent, t4.y), l2 = u2_lid(uent, t4.z),
+                          l3 = u2_lid(uent, t4.w);
+                if (l0) atomicOr(&Mw[l0], bits);
+                if (l1) atomicOr(&Mw[l1], bits);
+                if (l2) atomicOr(&Mw[l2], bits);
+                if (l3) atomicOr(&Mw[l3], bits);
+              }
+            }
+            wave_sync();
+            uint32_t acc = 0, mt = 0;
+#pragma unroll
+            for (int g = 0; g < kRegTok / 4; g++) {
+              if (g < ng) {
+                const uint32_t w0 = *reinterpret_cast<const uint32_t *>(Mb + ad[4 * g]);
+                const uint32_t w1 = *reinterpret_cast<const uint32_t *>(Mb + ad[4 * g + 1]);
+                const uint32_t w2 = *reinterpret_cast<const uint32_t *>(Mb + ad[4 * g + 2]);
+                const uint32_t w3 = *reinterpret_cast<const uint32_t *>(Mb + ad[4 * g + 3]);
+                mt += ((w0 >> 31) + (w1 >> 31)) + ((w2 >> 31) + (w3 >> 31));
+                acc |= (w0 | w1) | (w2 | w3);
+              }
+            }
+            if (maxb > kRegTok) {
+              for (int k = kRegTok; k < bl; k++) {
+                const uint32_t w = Mw[tp[k]];
+                mt += w >> 31;
+                acc |= w;
+              }
+            }
+            ms_acc += __popc(acc & ~kHitBit);
+            if (c == 0) mt_acc = mt;
+            wave_sync();
+            for (int k = lane; k < nq4; k += 64) reinterpret_cast<uint4 *>(Mw)[k] = make_uint4(0, 0, 0, 0);
+            wave_sync();
+          }
         }
         if (jok) {
           const int ms = (int)ms_acc, mt = (int)mt_acc;
@@ -398,7 +505,6 @@ __global__ __launch_bounds__(kSimThreads, 4) void sim_kernel(SimArgs a) {
   }
 }
 
-// --------------------------------------------- (a) similarity, bit-sliced tiles
 // The tile kernel computes the same counts as sim_kernel with far fewer
 // instructions per cell.  A work item is (pair, source rows [i0, i1)) with i0
 // a multiple of 128; wave w owns the 64-row strip starting at i0 + 64 w.
@@ -816,37 +922,51 @@ struct NwLane {
 
 // Scores of the next 16 steps for this lane.  Step t reads diagonal t-1 of
 // the strip; the cursor (diagonal d, its offset `base` in the strip block)
-// advances by one diagonal per step.  Lane 0 of strips after the first also
-// fetches the previous strip's bottom row value H[64s][t] for each step.
-__device__ __forceinline__ void nw_prefetch(float (&buf)[kNwUnroll], float (&rb)[kNwUnroll], const float *blk,
+// advances by one diagonal per step.  Lanes outside the diagonal read a
+// clamped in-range address (their value is never used).  For strips after
+// the first, lane k also fetches the previous strip's bottom-row value
+// H[64s][t] of the block's step k (handed to lane 0 by readlane).
+__device__ __forceinline__ void nw_prefetch(float (&buf)[kNwUnroll], float &rbv, const float *blk,
                                             const float *rowbuf, bool use_row, int &d, int &base, int lane, int R,
-                                            int m) {
+                                            int m, int last) {
+  const int t = d + 1 + lane;
+  rbv = (use_row && lane < kNwUnroll && t <= m) ? rowbuf[t] : 0.0f;
 #pragma unroll
   for (int k = 0; k < kNwUnroll; k++) {
-    const int c = d - lane;
     const int lo = max(0, d - m + 1);
     const int hi = min(R - 1, d);
-    const bool ok = lane < R && c >= 0 && c < m;
-    buf[k] = ok ? blk[base + lane - lo] : 0.0f;
-    const int t = d + 1;
-    rb[k] = (use_row && lane == 0 && t <= m) ? rowbuf[t] : 0.0f;
+    buf[k] = blk[min(max(base + lane - lo, 0), last)];
     base += max(0, hi - lo + 1);
     d++;
   }
 }
 
-// 16 steps of the strip sweep, written without divergent branches except
-// for the direction-word flush and the bottom-row hand-off (a few lanes).
-__device__ __forceinline__ void nw_steps(const float (&buf)[kNwUnroll], const float (&rb)[kNwUnroll], int t0,
-                                         int tend, NwLane &L, int lane, int s, int i, bool rowok, int lastlane,
-                                         int nstrips, int m, int W, float g, uint32_t *dirs, float *rowbuf) {
+// 16 steps of the strip sweep (t0 a multiple of 16).  Direction codes are
+// packed by step: bits 2k..2k+1 of a lane's word hold the code of its cell
+// at step t0 + k, and all lanes store their word once per block.  The last
+// row's H values are kept in registers and handed to the next strip at the
+// block's end.
+template <bool kTail, bool kTop>
+__device__ __forceinline__ void nw_steps(const float (&buf)[kNwUnroll], float rbv, int t0, int tend, NwLane &L,
+                                         int lane, int i, bool rowok, int lastlane, bool keep_row, int m, int Wr,
+                                         float g, uint32_t *dirs, float *rowbuf) {
+  float hb[kNwUnroll];
+  if (kTail) {
+#pragma unroll
+    for (int k = 0; k < kNwUnroll; k++) hb[k] = 0.0f;
+  }
 #pragma unroll
   for (int k = 0; k < kNwUnroll; k++) {
     const int t = t0 + k;
-    if (t > tend) break;
+    if (kTail && t > tend) break;
     const float from_left_lane = shift_up_one_lane(L.h);
-    L.topv = t == 0 ? 0.0f : __fadd_rn(L.topv, g);  // H[0][t], top boundary
-    const float up0 = s == 0 ? L.topv : rb[k];
+    float up0;
+    if (kTop) {
+      L.topv = t == 0 ? 0.0f : __fadd_rn(L.topv, g);  // H[0][t], top boundary
+      up0 = L.topv;
+    } else {
+      up0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(rbv), k));
+    }
     const float up = lane == 0 ? up0 : from_left_lane;
     const int j = t - lane;
     const bool act = rowok && j >= 0 && j <= m;
@@ -860,16 +980,25 @@ __device__ __forceinline__ void nw_steps(const float (&buf)[kNwUnroll], const fl
     best = l_wins ? ll : best;
     code = l_wins ? 2u : code;
     const float hn = j == 0 ? uu : best;  // column 0: H[i][0] = H[i-1][0] + g
-    const int jc = j - 1;
-    const bool cell = act && j >= 1;
-    L.dw |= cell ? code << (2 * (jc & 15)) : 0u;
-    if (cell && ((jc & 15) == 15 || j == m)) {
-      dirs[(int64_t)(i - 1) * W + (jc >> 4)] = L.dw;
-      L.dw = 0;
-    }
-    if (act && lane == lastlane && s + 1 < nstrips) rowbuf[j] = hn;
+    L.dw |= (act && j >= 1) ? code << (2 * k) : 0u;
+    hb[k] = hn;
     L.upv = act ? up : L.upv;
     L.h = act ? hn : L.h;
+  }
+  // this block's words: lane l's cells j = t - l in [1, m]
+  const int tl = kTail ? min(t0 + kNwUnroll - 1, tend) : t0 + kNwUnroll - 1;
+  if (rowok && tl >= lane + 1 && t0 <= lane + m) dirs[(int64_t)(i - 1) * Wr + ((t0 >> 4) - (lane >> 4))] = L.dw;
+  L.dw = 0;
+  if (keep_row) {
+    // lane k stores the last row's H at column t0 + k - lastlane
+    float v = 0.0f;
+#pragma unroll
+    for (int k = 0; k < kNwUnroll; k++) {
+      const float x = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(hb[k]), lastlane));
+      v = lane == k ? x : v;
+    }
+    const int j = t0 + lane - lastlane;
+    if (lane < kNwUnroll && j >= 0 && j <= m && t0 + lane <= tl) rowbuf[j] = v;
   }
 }
 
@@ -879,7 +1008,7 @@ __device__ __forceinline__ void nw_pair(const NwArgs &a, const PairDesc &d, int6
   const int lane = threadIdx.x;
   const int n = d.n, m = d.m;
   const float g = a.gap;
-  const int W = (m + 15) >> 4;
+  const int Wr = nw_dir_row_words(m);
   const float *S = a.S + d.s_off;
   float hnm = 0.0f;
 
@@ -890,18 +1019,38 @@ __device__ __forceinline__ void nw_pair(const NwArgs &a, const PairDesc &d, int6
       const bool rowok = i <= n;
       const int R = min(64, n - s * 64);
       const int lastlane = R - 1;
+      const bool keep_row = s + 1 < nstrips;
       const float *blk = S + (int64_t)(s * 64) * m;
+      const int last = R * m - 1;
       NwLane L{0.0f, 0.0f, 0.0f, 0u};
       const int tend = m + lastlane;
-      float bufA[kNwUnroll], bufB[kNwUnroll], rbA[kNwUnroll], rbB[kNwUnroll];
+      float bufA[kNwUnroll], bufB[kNwUnroll], rbA, rbB;
       int cd = -1, cbase = 0;  // prefetch cursor: step t reads diagonal t-1
       const bool use_row = s > 0;
-      nw_prefetch(bufA, rbA, blk, rowbuf, use_row, cd, cbase, lane, R, m);
-      for (int t0 = 0; t0 <= tend; t0 += 2 * kNwUnroll) {
-        nw_prefetch(bufB, rbB, blk, rowbuf, use_row, cd, cbase, lane, R, m);
-        nw_steps(bufA, rbA, t0, tend, L, lane, s, i, rowok, lastlane, nstrips, m, W, g, dirs, rowbuf);
-        nw_prefetch(bufA, rbA, blk, rowbuf, use_row, cd, cbase, lane, R, m);
-        nw_steps(bufB, rbB, t0 + kNwUnroll, tend, L, lane, s, i, rowok, lastlane, nstrips, m, W, g, dirs, rowbuf);
+      nw_prefetch(bufA, rbA, blk, rowbuf, use_row, cd, cbase, lane, R, m, last);
+      int t0 = 0;
+      // full blocks of 2 x 16 steps
+      for (; t0 + 2 * kNwUnroll - 1 <= tend; t0 += 2 * kNwUnroll) {
+        nw_prefetch(bufB, rbB, blk, rowbuf, use_row, cd, cbase, lane, R, m, last);
+        if (s == 0)
+          nw_steps<false, true>(bufA, rbA, t0, tend, L, lane, i, rowok, lastlane, keep_row, m, Wr, g, dirs, rowbuf);
+        else
+          nw_steps<false, false>(bufA, rbA, t0, tend, L, lane, i, rowok, lastlane, keep_row, m, Wr, g, dirs, rowbuf);
+        nw_prefetch(bufA, rbA, blk, rowbuf, use_row, cd, cbase, lane, R, m, last);
+        if (s == 0)
+          nw_steps<false, true>(bufB, rbB, t0 + kNwUnroll, tend, L, lane, i, rowok, lastlane, keep_row, m, Wr, g,
+                                dirs, rowbuf);
+        else
+          nw_steps<false, false>(bufB, rbB, t0 + kNwUnroll, tend, L, lane, i, rowok, lastlane, keep_row, m, Wr, g,
+                                 dirs, rowbuf);
+      }
+      // the rest: at most two blocks, the last one partial
+      for (; t0 <= tend; t0 += kNwUnroll) {
+        if (s == 0)
+          nw_steps<true, true>(bufA, rbA, t0, tend, L, lane, i, rowok, lastlane, keep_row, m, Wr, g, dirs, rowbuf);
+        else
+          nw_steps<true, false>(bufA, rbA, t0, tend, L, lane, i, rowok, lastlane, keep_row, m, Wr, g, dirs, rowbuf);
+        if (t0 + kNwUnroll <= tend) nw_prefetch(bufA, rbA, blk, rowbuf, use_row, cd, cbase, lane, R, m, last);
       }
       if (s == nstrips - 1) hnm = __shfl(L.h, lastlane);
       if (kLds)
@@ -926,13 +1075,13 @@ __device__ __forceinline__ void nw_pair(const NwArgs &a, const PairDesc &d, int6
     int64_t cur = -1;
     uint32_t word = 0;
     while (i > 0 && j > 0) {
-      const int jc = j - 1;
-      const int64_t widx = (int64_t)(i - 1) * W + (jc >> 4);
+      const int l = (i - 1) & 63, st = j + l;  // the cell's lane and sweep step
+      const int64_t widx = (int64_t)(i - 1) * Wr + ((st >> 4) - (l >> 4));
       if (widx != cur) {
         word = dirs[widx];
         cur = widx;
       }
-      const uint32_t code = (word >> (2 * (jc & 15))) & 3u;
+      const uint32_t code = (word >> (2 * (st & 15))) & 3u;
       char c;
       if (code == 0) {
         a.slot_src[slot_end - 1 - k] = i - 1;

@@ -101,14 +101,14 @@ void HostBuf::release() {
 
 // ------------------------------------------------------------------ plan
 // Per-pair requirement in workspace bytes (score block, scratch, slots).
-static inline bool nw_needs_global_dirs(int64_t n, int64_t m) { return n * ((m + 15) / 16) > kDirLds; }
+static inline bool nw_needs_global_dirs(int64_t n, int64_t m) { return n * nw_dir_row_words(m) > kDirLds; }
 static inline bool nw_needs_global_row(int64_t n, int64_t m) { return n > 64 && m + 1 > kRowLds; }
 
 size_t pair_bytes(int64_t n, int64_t m) {
   size_t b = sizeof(PairDesc) + 4 /*count*/ + 8 /*moves off*/;
   b += (size_t)((n + kItemRows - 1) / kItemRows) * sizeof(SimItem);
   b += (size_t)(n * m) * 4;
-  if (nw_needs_global_dirs(n, m)) b += (size_t)(n * ((m + 15) / 16)) * 4;
+  if (nw_needs_global_dirs(n, m)) b += (size_t)(n * nw_dir_row_words(m)) * 4;
   if (nw_needs_global_row(n, m)) b += (size_t)(m + 1) * 4;
   b += (size_t)std::min(n, m) * 12;
   return b;
@@ -129,7 +129,7 @@ ym_status Chunk::layout(const int64_t *sdo, const int64_t *tdo, int64_t p0_, int
     const int64_t n = sdo[p + 1] - sdo[p], m = tdo[p + 1] - tdo[p];
     if (n > 0 && m > 0) n_items += (n + kItemRows - 1) / kItemRows;
     cells += n * m;
-    if (nw_needs_global_dirs(n, m)) dir_words += n * ((m + 15) / 16);
+    if (nw_needs_global_dirs(n, m)) dir_words += n * nw_dir_row_words(m);
     if (nw_needs_global_row(n, m)) row_floats += m + 1;
     slots += std::min(n, m);
   }
@@ -178,7 +178,7 @@ void Chunk::fill_host(const int64_t *sdo, const int64_t *tdo, char *host) const 
     d.m = (int32_t)m;
     if (nw_needs_global_dirs(n, m)) {
       d.dir_off = dir_off;
-      dir_off += n * ((m + 15) / 16);
+      dir_off += n * nw_dir_row_words(m);
     } else {
       d.dir_off = -1;
     }

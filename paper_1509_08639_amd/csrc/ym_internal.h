@@ -25,10 +25,14 @@ constexpr int kTabLen = 64;             // score table covers sentence lengths <
 constexpr int kLogTabLen = 6;
 
 // NW kernel staging.
-constexpr int kDirLds = 2688;           // direction words held in LDS (covers 200 x 200)
+constexpr int kDirLds = 2816;           // direction words held in LDS (covers 200 x 200)
 constexpr int kRowLds = 512;            // boundary-row floats held in LDS
 
 static_assert((1 << kLogUcap) == kUcap, "hash capacity");
+
+// NW direction words per DP row: codes are packed 16 per word by sweep step,
+// and a row's m cells span at most ceil(m/16) + 1 words.
+__host__ __device__ constexpr int64_t nw_dir_row_words(int64_t m) { return (m + 15) / 16 + 1; }
 
 // One document pair of a chunk.
 struct PairDesc {
