@@ -29,6 +29,14 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Make one wave's global and LDS writes visible to its own later reads (a
+// one-wave workgroup: workgroup scope, no device-wide cache write-back).
+__device__ __forceinline__ void wave_sync_mem() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
 // ------------------------------------------------------------------ score
 // Section 4: the classifier's confidence is a probability.  Features are the
 // lexicon-overlap fractions f1 = m_s/a, f2 = m_t/b and the length ratio
@@ -170,24 +178,11 @@ __device__ __forceinline__ int block_excl_sum256(int v, int *sh, int *total) {
 
 __device__ __forceinline__ int64_t clamp64(int64_t v, int64_t lo, int64_t hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
-// Score layout.  A pair's n x m score block is stored strip by strip (64 rows
-// per strip, the last one R = n mod 64 rows), and inside a strip by anti-
-// diagonals: cell (l, c) of an R x m strip sits at diag_base(l + c) plus its
-// rank on that diagonal.  The NW sweep below visits exactly one diagonal per
-// step, so each step reads one contiguous run of scores.
-__device__ __forceinline__ int64_t tri(int64_t x) { return x > 0 ? x * (x + 1) / 2 : 0; }
-
-// number of cells of an R x m block on diagonals before t
-__device__ __forceinline__ int64_t diag_base(int64_t t, int64_t R, int64_t m) {
-  return tri(t) - tri(t - R) - tri(t - m) + tri(t - R - m);
-}
-
-// offset of score (i, c) inside its pair's block
+// offset of score (i, c) inside its pair's block (layout: score_slots)
 __device__ __forceinline__ int64_t score_pos(int i, int c, int n, int m) {
   const int s = i >> 6, l = i & 63;
   const int R = min(64, n - (s << 6));
-  const int t = l + c;
-  return (int64_t)(s << 6) * m + diag_base(t, R, m) + l - max(0, t - m + 1);
+  return (int64_t)s * (m + 63) * 64 + (int64_t)(l + c) * R + l;
 }
 
 // ------------------------------------------------------ (a) similarity
@@ -213,19 +208,6 @@ __device__ __forceinline__ int wave_max(int v) {
   return v;
 }
 
-// score_pos in 32-bit arithmetic when the diagonal index stays below 65063
-__device__ __forceinline__ int64_t score_pos_fast(int i, int c, int n, int m) {
-  if (m < 65000) {
-    const int s = i >> 6, l = i & 63;
-    const int R = min(64, n - (s << 6));
-    const int t = l + c;
-    auto tri32 = [](int x) -> uint32_t { return x > 0 ? (uint32_t)x * (uint32_t)(x + 1) / 2u : 0u; };
-    const uint32_t db = tri32(t) - tri32(t - R) - tri32(t - m) + tri32(t - R - m);
-    return (int64_t)(s << 6) * m + (int64_t)db + l - max(0, t - m + 1);
-  }
-  return score_pos(i, c, n, m);
-}
-
 // LDS hash entry of the lanes kernel: key and its dense local id side by
 // side, so a lookup is one 8-byte read.
 __device__ __forceinline__ int u2_insert(int2 *ent, int32_t x) {
@@ -249,6 +231,14 @@ __device__ __forceinline__ int u2_lid(const int2 *ent, int32_t x) {
   return e.x == x ? e.y : 0;
 }
 
+__device__ __forceinline__ int64_t readlane64(int64_t v, int k) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, k);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), k);
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+static_assert(kItemRows / kSimWaves <= 64, "one lane per row of a wave");
+
 __global__ __launch_bounds__(kSimThreads, 4) void sim_kernel(SimArgs a) {
   __shared__ int2 uent[kUcap];
   __shared__ __align__(16) uint16_t tdoc[kTdocCap];
@@ -271,6 +261,16 @@ __global__ __launch_bounds__(kSimThreads, 4) void sim_kernel(SimArgs a) {
     if (m <= 0 || it.i1 <= it.i0) continue;
     const int64_t *toffs = a.tgt_sent_off + d.tgt_sent0;
     const int64_t *soffs = a.src_sent_off + d.src_sent0;
+    // this wave's source rows and their token ranges (lane k: row k)
+    const int nrows = max(0, (it.i1 - it.i0 - wv + kSimWaves - 1) / kSimWaves);
+    int64_t rsb = 0;
+    int rlen = 0;
+    if (lane < nrows) {
+      const int ii = it.i0 + wv + kSimWaves * lane;
+      rsb = clamp64(soffs[ii], 0, a.n_src_tok);
+      const int64_t se = clamp64(soffs[ii + 1], rsb, a.n_src_tok);
+      rlen = (int)min(se - rsb, (int64_t)0x7fffffff);
+    }
 
     for (int j0 = 0; j0 < m;) {
       if (tid == 0) {
@@ -353,21 +353,22 @@ __global__ __launch_bounds__(kSimThreads, 4) void sim_kernel(SimArgs a) {
       const int ng = (min(maxb, kRegTok) + 3) >> 2;
       const int nq4 = (nlid + 3) >> 2;
 
-      // translations of the wave's next source sentence (positions < 64) are
-      // fetched one sentence ahead
-      auto fetch = [&](int ii) -> int4 {
-        if (ii >= it.i1) return make_int4(-1, -1, -1, -1);
-        const int64_t b0 = clamp64(soffs[ii], 0, a.n_src_tok);
-        const int64_t b1 = clamp64(soffs[ii + 1], b0, a.n_src_tok);
-        return lane < b1 - b0 ? a.trans[b0 + lane] : make_int4(-1, -1, -1, -1);
+      // Row k of this wave is source sentence i = i0 + wv + 4k; lane k holds
+      // its token range.  The translations of row k + 1 (positions < 64) are
+      // fetched while row k is worked on (two register sets, no copy), and a
+      // row's scores are stored while the next row is worked on.
+      auto fetch = [&](int k) -> int4 {
+        if (k >= nrows) return make_int4(-1, -1, -1, -1);
+        const int64_t b0 = readlane64(rsb, k);
+        const int len = __builtin_amdgcn_readlane(rlen, k);
+        return lane < len ? a.trans[b0 + lane] : make_int4(-1, -1, -1, -1);
       };
-      int4 pre = fetch(it.i0 + wv);
-      for (int i = it.i0 + wv; i < it.i1; i += kSimWaves) {
-        const int64_t sb = clamp64(soffs[i], 0, a.n_src_tok);
-        const int64_t se = clamp64(soffs[i + 1], sb, a.n_src_tok);
-        const int ai = (int)min(se - sb, (int64_t)0x7fffffff);
-        const int4 cur = pre;
-        pre = fetch(i + kSimWaves);
+      float *pend_dst = nullptr;
+      float pend_sv = 0.0f;
+      auto row = [&](const int k, const int4 cur) {
+        const int i = it.i0 + wv + kSimWaves * k;
+        const int64_t sb = readlane64(rsb, k);
+        const int ai = __builtin_amdgcn_readlane(rlen, k);
         uint32_t ms_acc = 0, mt_acc = 0;
         if (ai <= 64) {
           // one token per lane: its (at most four) local ids stay in registers
@@ -486,19 +487,34 @@ __global__ __launch_bounds__(kSimThreads, 4) void sim_kernel(SimArgs a) {
             wave_sync();
           }
         }
+        // The score is stored one source sentence later, so the table read
+        // is not waited for before the next sentence's work.
+        float sv = 0.0f;
+        float *dst = nullptr;
         if (jok) {
           const int ms = (int)ms_acc, mt = (int)mt_acc;
-          const float sv = (ai < kTabLen && bl < kTabLen)
-                               ? a.table[((ai * kTabLen + bl) * kTabLen + ms) * kTabLen + mt]
-                               : score_direct(a.w0, a.w1, a.w2, a.w3, ms, ai, mt, bl);
-          a.S[d.s_off + score_pos_fast(i, j0 + lane, n, m)] = sv;
+          sv = (ai < kTabLen && bl < kTabLen) ? a.table[((ai * kTabLen + bl) * kTabLen + ms) * kTabLen + mt]
+                                              : score_direct(a.w0, a.w1, a.w2, a.w3, ms, ai, mt, bl);
+          dst = a.S + d.s_off + score_pos(i, j0 + lane, n, m);
           if (a.ms_out) {
-            const int64_t cell = d.s_off + (int64_t)i * m + j0 + lane;
+            const int64_t cell = d.rm_off + (int64_t)i * m + j0 + lane;
             a.ms_out[cell] = ms;
             a.mt_out[cell] = mt;
           }
         }
+        if (pend_dst) *pend_dst = pend_sv;
+        pend_dst = dst;
+        pend_sv = sv;
+      };
+      int4 bufA = fetch(0), bufB;
+      for (int k = 0; k < nrows; k += 2) {
+        bufB = fetch(k + 1);
+        row(k, bufA);
+        if (k + 1 >= nrows) break;
+        bufA = fetch(k + 2);
+        row(k + 1, bufB);
       }
+      if (pend_dst) *pend_dst = pend_sv;
       __syncthreads();
       j0 = j1;
     }
@@ -688,20 +704,13 @@ __device__ __forceinline__ void tile_work(const SimArgs &a, const PairDesc &d, c
   wave_sync();
   const int n = d.n, m = d.m;
   const int c = t.j0 + lane;
-  if (NPL == kFastPlanes && m < 65000) {
+  if (NPL == kFastPlanes) {
     // Cells l0 + 8k (k = 0..3) of a 32-row half at once: one shift and mask
-    // per plane gathers their bits into four bytes.  Four cursors follow the
-    // diagonals l0 + 8k + c of the strip-diagonal layout.
-    auto tri32 = [](int x) -> uint32_t { return x > 0 ? (uint32_t)x * (uint32_t)(x + 1) / 2u : 0u; };
-    auto delta = [&](int tt) -> uint32_t { return tri32(tt) - tri32(tt - R) - tri32(tt - m) + tri32(tt - R - m); };
-    auto cnt = [&](int tt) -> uint32_t { return (uint32_t)max(0, min(R - 1, tt) - max(0, tt - m + 1) + 1); };
-    float *strip = a.S + d.s_off + (int64_t)r0 * m;
+    // per plane gathers their bits into four bytes.
+    float *strip = a.S + d.s_off + (int64_t)(r0 >> 6) * (m + 63) * 64;
     const uint32_t bl6 = (uint32_t)t.bl << (2 * kLogTabLen);
     for (int h = 0; h < 2; h++) {
       if (32 * h >= R) break;
-      uint32_t cur[4];
-#pragma unroll
-      for (int k = 0; k < 4; k++) cur[k] = delta(32 * h + 8 * k + c);
       for (int l0 = 0; l0 < 8; l0++) {
         uint32_t ms4 = 0, mt4 = 0;
 #pragma unroll
@@ -722,10 +731,9 @@ __device__ __forceinline__ void tile_work(const SimArgs &a, const PairDesc &d, c
           const uint32_t ms = (ms4 >> (8 * k)) & 0xFFu, mt = (mt4 >> (8 * k)) & 0xFFu;
           const uint32_t idx = ((ai << (3 * kLogTabLen)) | bl6) | (ms << kLogTabLen) | mt;
           sv[k] = ok[k] ? a.table[idx] : 0.0f;
-          pos[k] = (int64_t)cur[k] + l - max(0, tt - m + 1);
-          cur[k] += cnt(tt);
+          pos[k] = (int64_t)tt * R + l;
           if (ok[k] && a.ms_out) {
-            const int64_t cell = d.s_off + (int64_t)(r0 + l) * m + c;
+            const int64_t cell = d.rm_off + (int64_t)(r0 + l) * m + c;
             a.ms_out[cell] = (int32_t)ms;
             a.mt_out[cell] = (int32_t)mt;
           }
@@ -745,7 +753,7 @@ __device__ __forceinline__ void tile_work(const SimArgs &a, const PairDesc &d, c
                              : score_direct(a.w0, a.w1, a.w2, a.w3, ms, ai, mt, t.bl);
         a.S[d.s_off + score_pos(r0 + l, c, n, m)] = sv;
         if (a.ms_out) {
-          const int64_t cell = d.s_off + (int64_t)(r0 + l) * m + c;
+          const int64_t cell = d.rm_off + (int64_t)(r0 + l) * m + c;
           a.ms_out[cell] = ms;
           a.mt_out[cell] = mt;
         }
@@ -891,9 +899,9 @@ __global__ __launch_bounds__(256) void relayout_kernel(const PairDesc *descs, in
     const int i = (int)(k / d.m), c = (int)(k % d.m);
     const int64_t q = score_pos(i, c, d.n, d.m);
     if (to_diag)
-      dst[d.s_off + q] = src[d.s_off + k];
+      dst[d.s_off + q] = src[d.rm_off + k];
     else
-      dst[d.s_off + k] = src[d.s_off + q];
+      dst[d.rm_off + k] = src[d.s_off + q];
   }
 }
 
@@ -914,38 +922,40 @@ __device__ __forceinline__ float shift_up_one_lane(float v) {
 }
 
 constexpr int kNwUnroll = 16;
+// Word 3 of a raw buffer resource on gfx9-family GPUs (32-bit data format).
+constexpr int kBufferFlags = 0x00020000;
 
 struct NwLane {
   float h, upv, topv;
   uint32_t dw;
 };
 
-// Scores of the next 16 steps for this lane.  Step t reads diagonal t-1 of
-// the strip; the cursor (diagonal d, its offset `base` in the strip block)
-// advances by one diagonal per step.  Lanes outside the diagonal read a
-// clamped in-range address (their value is never used).  For strips after
-// the first, lane k also fetches the previous strip's bottom-row value
-// H[64s][t] of the block's step k (handed to lane 0 by readlane).
-__device__ __forceinline__ void nw_prefetch(float (&buf)[kNwUnroll], float &rbv, const float *blk,
-                                            const float *rowbuf, bool use_row, int &d, int &base, int lane, int R,
-                                            int m, int last) {
+// Scores of the next 16 steps for this lane: step t reads slot
+// (t - 1) * R + lane of the strip (anti-diagonal t - 1).  The strip is read
+// through a buffer resource whose range is the strip, so reads before its
+// first or after its last slot return 0 without touching memory; the values
+// of lanes outside a diagonal are never used.  For strips after the first,
+// lane k also fetches the previous strip's bottom-row value H[64s][t] of the
+// block's step k (handed to lane 0 by readlane).
+__device__ __forceinline__ void nw_prefetch(float (&buf)[kNwUnroll], float &rbv, __amdgpu_buffer_rsrc_t rs,
+                                            const float *rowbuf, bool use_row, int &d, int lane, int R, int m) {
   const int t = d + 1 + lane;
   rbv = (use_row && lane < kNwUnroll && t <= m) ? rowbuf[t] : 0.0f;
 #pragma unroll
   for (int k = 0; k < kNwUnroll; k++) {
-    const int lo = max(0, d - m + 1);
-    const int hi = min(R - 1, d);
-    buf[k] = blk[min(max(base + lane - lo, 0), last)];
-    base += max(0, hi - lo + 1);
+    buf[k] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (d * R + lane) * 4, 0, 0));
     d++;
   }
 }
 
-// 16 steps of the strip sweep (t0 a multiple of 16).  Direction codes are
-// packed by step: bits 2k..2k+1 of a lane's word hold the code of its cell
-// at step t0 + k, and all lanes store their word once per block.  The last
-// row's H values are kept in registers and handed to the next strip at the
-// block's end.
+// 16 steps of the strip sweep (t0 a multiple of 16).  Lane l holds DP row
+// i = 64s + l + 1 and computes column j = t - l at step t.  Steps with j < 0
+// or j > m (and rows past n) compute values that are never read: column 0
+// (j = 0) depends only on the lane above, and a lane only ever reads the lane
+// above at the column it is itself computing.  Direction codes are packed by
+// step: bits 2k..2k+1 of a lane's word hold the code of its cell at step
+// t0 + k, and every lane stores its word once per block.  The last row's H
+// values are kept in registers and handed to the next strip at the block end.
 template <bool kTail, bool kTop>
 __device__ __forceinline__ void nw_steps(const float (&buf)[kNwUnroll], float rbv, int t0, int tend, NwLane &L,
                                          int lane, int i, bool rowok, int lastlane, bool keep_row, int m, int Wr,
@@ -955,6 +965,7 @@ __device__ __forceinline__ void nw_steps(const float (&buf)[kNwUnroll], float rb
 #pragma unroll
     for (int k = 0; k < kNwUnroll; k++) hb[k] = 0.0f;
   }
+  uint32_t dw = 0;
 #pragma unroll
   for (int k = 0; k < kNwUnroll; k++) {
     const int t = t0 + k;
@@ -962,14 +973,12 @@ __device__ __forceinline__ void nw_steps(const float (&buf)[kNwUnroll], float rb
     const float from_left_lane = shift_up_one_lane(L.h);
     float up0;
     if (kTop) {
-      L.topv = t == 0 ? 0.0f : __fadd_rn(L.topv, g);  // H[0][t], top boundary
+      L.topv = __fadd_rn(L.topv, g);  // H[0][t] (starts at -g: -g + g = +0 at t = 0)
       up0 = L.topv;
     } else {
       up0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(rbv), k));
     }
     const float up = lane == 0 ? up0 : from_left_lane;
-    const int j = t - lane;
-    const bool act = rowok && j >= 0 && j <= m;
     const float dd = __fadd_rn(L.upv, buf[k]);
     const float uu = __fadd_rn(up, g);
     const float ll = __fadd_rn(L.h, g);
@@ -979,16 +988,15 @@ __device__ __forceinline__ void nw_steps(const float (&buf)[kNwUnroll], float rb
     const bool l_wins = ll > best;
     best = l_wins ? ll : best;
     code = l_wins ? 2u : code;
-    const float hn = j == 0 ? uu : best;  // column 0: H[i][0] = H[i-1][0] + g
-    L.dw |= (act && j >= 1) ? code << (2 * k) : 0u;
+    const float hn = lane == t ? uu : best;  // column 0: H[i][0] = H[i-1][0] + g
+    dw |= code << (2 * k);
     hb[k] = hn;
-    L.upv = act ? up : L.upv;
-    L.h = act ? hn : L.h;
+    L.upv = up;
+    L.h = hn;
   }
   // this block's words: lane l's cells j = t - l in [1, m]
   const int tl = kTail ? min(t0 + kNwUnroll - 1, tend) : t0 + kNwUnroll - 1;
-  if (rowok && tl >= lane + 1 && t0 <= lane + m) dirs[(int64_t)(i - 1) * Wr + ((t0 >> 4) - (lane >> 4))] = L.dw;
-  L.dw = 0;
+  if (rowok && tl >= lane + 1 && t0 <= lane + m) dirs[(int64_t)(i - 1) * Wr + ((t0 >> 4) - (lane >> 4))] = dw;
   if (keep_row) {
     // lane k stores the last row's H at column t0 + k - lastlane
     float v = 0.0f;
@@ -1020,23 +1028,24 @@ __device__ __forceinline__ void nw_pair(const NwArgs &a, const PairDesc &d, int6
       const int R = min(64, n - s * 64);
       const int lastlane = R - 1;
       const bool keep_row = s + 1 < nstrips;
-      const float *blk = S + (int64_t)(s * 64) * m;
-      const int last = R * m - 1;
-      NwLane L{0.0f, 0.0f, 0.0f, 0u};
+      const float *blk = S + (int64_t)s * (m + 63) * 64;
+      const __amdgpu_buffer_rsrc_t rs =
+          __builtin_amdgcn_make_buffer_rsrc((void *)blk, (short)0, (int)((m + R - 1) * R * 4), kBufferFlags);
+      NwLane L{0.0f, 0.0f, -g, 0u};
       const int tend = m + lastlane;
       float bufA[kNwUnroll], bufB[kNwUnroll], rbA, rbB;
-      int cd = -1, cbase = 0;  // prefetch cursor: step t reads diagonal t-1
+      int cd = -1;  // prefetch cursor: step t reads diagonal t-1
       const bool use_row = s > 0;
-      nw_prefetch(bufA, rbA, blk, rowbuf, use_row, cd, cbase, lane, R, m, last);
+      nw_prefetch(bufA, rbA, rs, rowbuf, use_row, cd, lane, R, m);
       int t0 = 0;
       // full blocks of 2 x 16 steps
       for (; t0 + 2 * kNwUnroll - 1 <= tend; t0 += 2 * kNwUnroll) {
-        nw_prefetch(bufB, rbB, blk, rowbuf, use_row, cd, cbase, lane, R, m, last);
+        nw_prefetch(bufB, rbB, rs, rowbuf, use_row, cd, lane, R, m);
         if (s == 0)
           nw_steps<false, true>(bufA, rbA, t0, tend, L, lane, i, rowok, lastlane, keep_row, m, Wr, g, dirs, rowbuf);
         else
           nw_steps<false, false>(bufA, rbA, t0, tend, L, lane, i, rowok, lastlane, keep_row, m, Wr, g, dirs, rowbuf);
-        nw_prefetch(bufA, rbA, blk, rowbuf, use_row, cd, cbase, lane, R, m, last);
+        nw_prefetch(bufA, rbA, rs, rowbuf, use_row, cd, lane, R, m);
         if (s == 0)
           nw_steps<false, true>(bufB, rbB, t0 + kNwUnroll, tend, L, lane, i, rowok, lastlane, keep_row, m, Wr, g,
                                 dirs, rowbuf);
@@ -1050,14 +1059,10 @@ __device__ __forceinline__ void nw_pair(const NwArgs &a, const PairDesc &d, int6
           nw_steps<true, true>(bufA, rbA, t0, tend, L, lane, i, rowok, lastlane, keep_row, m, Wr, g, dirs, rowbuf);
         else
           nw_steps<true, false>(bufA, rbA, t0, tend, L, lane, i, rowok, lastlane, keep_row, m, Wr, g, dirs, rowbuf);
-        if (t0 + kNwUnroll <= tend) nw_prefetch(bufA, rbA, blk, rowbuf, use_row, cd, cbase, lane, R, m, last);
+        if (t0 + kNwUnroll <= tend) nw_prefetch(bufA, rbA, rs, rowbuf, use_row, cd, lane, R, m);
       }
       if (s == nstrips - 1) hnm = __shfl(L.h, lastlane);
-      if (kLds)
-        wave_sync();
-      else
-        __threadfence();
-      __builtin_amdgcn_wave_barrier();
+      wave_sync_mem();
     }
   } else {
     float h = 0.0f;
@@ -1065,65 +1070,113 @@ __device__ __forceinline__ void nw_pair(const NwArgs &a, const PairDesc &d, int6
     hnm = h;
   }
 
-  // traceback (lane 0)
+  // traceback
   const int cap = min(n, m);
   const int64_t slot_end = d.out_off + cap;
   char *mv = a.moves ? a.moves + a.moves_off[p] : nullptr;
   int K = 0, T = 0;
-  if (lane == 0) {
-    int i = n, j = m, k = 0, t = 0;
-    int64_t cur = -1;
-    uint32_t word = 0;
+  if (mv) {
+    // with the move string (debug entry): lane 0, one move at a time
+    if (lane == 0) {
+      int i = n, j = m, k = 0, t = 0;
+      int64_t cur = -1;
+      uint32_t word = 0;
+      while (i > 0 && j > 0) {
+        const int l = (i - 1) & 63, st = j + l;  // the cell's lane and sweep step
+        const int64_t widx = (int64_t)(i - 1) * Wr + ((st >> 4) - (l >> 4));
+        if (widx != cur) {
+          word = dirs[widx];
+          cur = widx;
+        }
+        const uint32_t code = (word >> (2 * (st & 15))) & 3u;
+        char c;
+        if (code == 0) {
+          a.slot_src[slot_end - 1 - k] = i - 1;
+          a.slot_tgt[slot_end - 1 - k] = j - 1;
+          k++;
+          i--;
+          j--;
+          c = 'D';
+        } else if (code == 1) {
+          i--;
+          c = 'U';
+        } else {
+          j--;
+          c = 'L';
+        }
+        mv[(n + m - 1) - t] = c;
+        t++;
+      }
+      while (i > 0) {
+        i--;
+        mv[(n + m - 1) - t] = 'U';
+        t++;
+      }
+      while (j > 0) {
+        j--;
+        mv[(n + m - 1) - t] = 'L';
+        t++;
+      }
+      K = k;
+      T = t;
+    }
+    K = __shfl(K, 0);
+    T = __shfl(T, 0);
+  } else {
+    // wave-uniform walk (scalar unit).  Inside one direction word a run of L
+    // moves is skipped at once: the next cell that is not an L move is the
+    // highest code below the current position that is not 2.  Lane (k mod 64)
+    // keeps the k-th diagonal move; each full batch of 64 is stored at once.
+    int i = n, j = m, k = 0;
+    int vs = 0, vt = 0;
     while (i > 0 && j > 0) {
-      const int l = (i - 1) & 63, st = j + l;  // the cell's lane and sweep step
+      const int l = (i - 1) & 63, st = j + l;
       const int64_t widx = (int64_t)(i - 1) * Wr + ((st >> 4) - (l >> 4));
-      if (widx != cur) {
-        word = dirs[widx];
-        cur = widx;
+      const uint32_t word =
+          (uint32_t)__builtin_amdgcn_readfirstlane((int)(kLds ? dirs[widx] : ((volatile const uint32_t *)dirs)[widx]));
+      const int pos = st & 15;
+      const uint32_t notL = ~(word >> 1) & 0x55555555u & (0xFFFFFFFFu >> (30 - 2 * pos));
+      if (notL == 0) {  // L moves down to the word's first step
+        j -= min(pos + 1, j);
+        continue;
       }
-      const uint32_t code = (word >> (2 * (st & 15))) & 3u;
-      char c;
-      if (code == 0) {
-        a.slot_src[slot_end - 1 - k] = i - 1;
-        a.slot_tgt[slot_end - 1 - k] = j - 1;
+      const int q = (31 - __builtin_clz(notL)) >> 1;
+      if (j - (pos - q) < 1) {  // the L run reaches column 0 first
+        j = 0;
+        break;
+      }
+      j -= pos - q;
+      if (((word >> (2 * q)) & 3u) == 0u) {
+        if (lane == (k & 63)) {
+          vs = i - 1;
+          vt = j - 1;
+        }
         k++;
-        i--;
+        if ((k & 63) == 0) {
+          const int64_t r = slot_end - k + 63 - lane;  // move k - 64 + lane
+          a.slot_src[r] = vs;
+          a.slot_tgt[r] = vt;
+        }
         j--;
-        c = 'D';
-      } else if (code == 1) {
-        i--;
-        c = 'U';
-      } else {
-        j--;
-        c = 'L';
       }
-      if (mv) mv[(n + m - 1) - t] = c;
-      t++;
-    }
-    while (i > 0) {
       i--;
-      if (mv) mv[(n + m - 1) - t] = 'U';
-      t++;
     }
-    while (j > 0) {
-      j--;
-      if (mv) mv[(n + m - 1) - t] = 'L';
-      t++;
+    if (lane < (k & 63)) {
+      const int64_t r = slot_end - 1 - ((k & ~63) + lane);
+      a.slot_src[r] = vs;
+      a.slot_tgt[r] = vt;
     }
     K = k;
-    T = t;
+    T = n + m - k;
   }
-  K = __shfl(K, 0);
-  T = __shfl(T, 0);
-  __threadfence();
-  __builtin_amdgcn_wave_barrier();
+  wave_sync_mem();
   if (mv) {  // move the forward path from the tail of the region to its front
     const int off = n + m - T;
     for (int b = 0; b < T; b += 64) {
-      const int k = b + lane;
-      const char c = k < T ? mv[off + k] : 0;
+      const int kk = b + lane;
+      const char c = kk < T ? mv[off + kk] : 0;
       __builtin_amdgcn_wave_barrier();
-      if (k < T) mv[k] = c;
+      if (kk < T) mv[kk] = c;
     }
   }
 

@@ -107,7 +107,7 @@ static inline bool nw_needs_global_row(int64_t n, int64_t m) { return n > 64 && 
 size_t pair_bytes(int64_t n, int64_t m) {
   size_t b = sizeof(PairDesc) + 4 /*count*/ + 8 /*moves off*/;
   b += (size_t)((n + kItemRows - 1) / kItemRows) * sizeof(SimItem);
-  b += (size_t)(n * m) * 4;
+  b += (size_t)score_slots(n, m) * 4;
   if (nw_needs_global_dirs(n, m)) b += (size_t)(n * nw_dir_row_words(m)) * 4;
   if (nw_needs_global_row(n, m)) b += (size_t)(m + 1) * 4;
   b += (size_t)std::min(n, m) * 12;
@@ -122,6 +122,7 @@ ym_status Chunk::layout(const int64_t *sdo, const int64_t *tdo, int64_t p0_, int
   np = p1 - p0;
   n_items = 0;
   cells = 0;
+  s_slots = 0;
   dir_words = 0;
   row_floats = 0;
   slots = 0;
@@ -129,6 +130,7 @@ ym_status Chunk::layout(const int64_t *sdo, const int64_t *tdo, int64_t p0_, int
     const int64_t n = sdo[p + 1] - sdo[p], m = tdo[p + 1] - tdo[p];
     if (n > 0 && m > 0) n_items += (n + kItemRows - 1) / kItemRows;
     cells += n * m;
+    s_slots += score_slots(n, m);
     if (nw_needs_global_dirs(n, m)) dir_words += n * nw_dir_row_words(m);
     if (nw_needs_global_row(n, m)) row_floats += m + 1;
     slots += std::min(n, m);
@@ -139,7 +141,7 @@ ym_status Chunk::layout(const int64_t *sdo, const int64_t *tdo, int64_t p0_, int
   off_items = o;
   o = align256(o + (size_t)std::max<int64_t>(n_items, 1) * sizeof(SimItem));
   off_S = o;
-  o = align256(o + (size_t)cells * 4);
+  o = align256(o + (size_t)s_slots * 4);
   off_dirs = o;
   o = align256(o + (size_t)dir_words * 4);
   off_rows = o;
@@ -166,13 +168,14 @@ void Chunk::fill_host(const int64_t *sdo, const int64_t *tdo, char *host) const 
   SimItem *items = (SimItem *)(host + align256((size_t)np * sizeof(PairDesc)));
   int64_t *moff = (int64_t *)(host + align256((size_t)np * sizeof(PairDesc)) +
                               align256((size_t)std::max<int64_t>(n_items, 1) * sizeof(SimItem)));
-  int64_t s_off = 0, out_off = 0, dir_off = 0, row_off = 0, mv = 0, it = 0;
+  int64_t s_off = 0, rm_off = 0, out_off = 0, dir_off = 0, row_off = 0, mv = 0, it = 0;
   for (int64_t p = p0; p < p1; p++) {
     const int64_t n = sdo[p + 1] - sdo[p], m = tdo[p + 1] - tdo[p];
     PairDesc &d = descs[p - p0];
     d.src_sent0 = sdo[p];
     d.tgt_sent0 = tdo[p];
     d.s_off = s_off;
+    d.rm_off = rm_off;
     d.out_off = out_off;
     d.n = (int32_t)n;
     d.m = (int32_t)m;
@@ -198,7 +201,8 @@ void Chunk::fill_host(const int64_t *sdo, const int64_t *tdo, char *host) const 
       }
     moff[p - p0] = mv;
     mv += n + m;
-    s_off += n * m;
+    s_off += score_slots(n, m);
+    rm_off += n * m;
     out_off += std::min(n, m);
   }
 }
@@ -484,6 +488,9 @@ ym_status plan_chunks(const int64_t *sdo, const int64_t *tdo, int64_t n_pairs, s
                       std::vector<std::pair<int64_t, int64_t>> &chunks) {
   chunks.clear();
   int64_t p = 0;
+  for (int64_t q = 0; q < n_pairs; q++)
+    if (sdo[q + 1] - sdo[q] > kMaxDocSents || tdo[q + 1] - tdo[q] > kMaxDocSents)
+      return fail(YM_EINVAL, "pair %lld: a document has more than %lld sentences", (long long)q, (long long)kMaxDocSents);
   while (p < n_pairs) {
     size_t acc = kChunkSlack;
     int64_t q = p;

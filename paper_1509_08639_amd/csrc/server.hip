@@ -377,6 +377,8 @@ ym_status ym_submit(ym_server *S, const ym_batch *b, uint64_t *ticket) {
   if ((s = check_doc_off(b->src_doc_off, 1, "src_doc_off")) || (s = check_doc_off(b->tgt_doc_off, 1, "tgt_doc_off")))
     return s;
   const int64_t n = b->src_doc_off[1], m = b->tgt_doc_off[1];
+  if (n > kMaxDocSents || m > kMaxDocSents)
+    return fail(YM_EINVAL, "a document has more than %lld sentences", (long long)kMaxDocSents);
   if (!b->src_sent_off || !b->tgt_sent_off) return fail(YM_EINVAL, "NULL sentence offsets");
   if (b->src_sent_off[0] != 0 || b->tgt_sent_off[0] != 0) return fail(YM_EINVAL, "sentence offsets must start at 0");
   for (int64_t i = 0; i < n; i++) {

@@ -21,6 +21,7 @@ constexpr int kTdocCap = kTcap + 3 * kJcap;  // staged ids, each sentence padded
 static_assert(kJcap <= kSimThreads && kJcap == 64, "one lane per target sentence of a chunk");
 constexpr int kItemRows = 128;          // source sentences per work item (two 64-row strips)
 constexpr int kMaxSentTokens = 1024;    // longest sentence the host entry points accept
+constexpr int64_t kMaxDocSents = 1 << 22;  // most sentences per document (one score strip stays below 2 GiB)
 constexpr int kTabLen = 64;             // score table covers sentence lengths < 64
 constexpr int kLogTabLen = 6;
 
@@ -34,6 +35,16 @@ static_assert((1 << kLogUcap) == kUcap, "hash capacity");
 // and a row's m cells span at most ceil(m/16) + 1 words.
 __host__ __device__ constexpr int64_t nw_dir_row_words(int64_t m) { return (m + 15) / 16 + 1; }
 
+// Score layout of one n x m block: rows in strips of 64 (the last one has
+// R = n - 64 (strips - 1) rows); inside a strip, anti-diagonal t = l + c is a
+// row of R slots and cell (l, c) sits at t * R + l.  A strip holds
+// (m + R - 1) * R slots, of which R * m are cells; the NW sweep reads one
+// anti-diagonal per step as one contiguous run.
+__host__ __device__ constexpr int64_t score_slots(int64_t n, int64_t m) {
+  return (n <= 0 || m <= 0) ? 0
+                            : ((n - 1) / 64) * (m + 63) * 64 + (m + (n - 64 * ((n - 1) / 64)) - 1) * (n - 64 * ((n - 1) / 64));
+}
+
 // One document pair of a chunk.
 struct PairDesc {
   int64_t src_sent0;  // global index of its first source sentence
@@ -42,6 +53,7 @@ struct PairDesc {
   int64_t out_off;    // offset of its min(n, m) output slots
   int64_t dir_off;    // offset of its direction words in global scratch (-1: LDS)
   int64_t row_off;    // offset of its boundary row in global scratch (-1: LDS)
+  int64_t rm_off;     // offset of its n x m block in row-major debug buffers
   int32_t n, m;
 };
 
