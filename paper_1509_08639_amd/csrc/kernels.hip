@@ -239,20 +239,20 @@ __device__ __forceinline__ int64_t readlane64(int64_t v, int k) {
 
 static_assert(kItemRows / kSimWaves <= 64, "one lane per row of a wave");
 
-__global__ __launch_bounds__(kSimThreads, 4) void sim_kernel(SimArgs a) {
+__global__ __launch_bounds__(kSimThreads, 3) void sim_kernel(SimArgs a) {
   __shared__ int2 uent[kUcap];
   __shared__ __align__(16) uint16_t tdoc[kTdocCap];
   __shared__ uint16_t toff[kJcap];        // start of sentence jj in the padded staging
   __shared__ uint16_t toff_o[kJcap + 1];  // start of sentence jj in the chunk's token range
   __shared__ uint16_t tlen[kJcap];
-  __shared__ __align__(16) uint32_t Mw_all[kSimWaves][kTcap + 4];
+  __shared__ __align__(16) uint2 Mw2[kSimWaves][kTcap + 4];  // per wave and local id: two mask words
   __shared__ int sh_scan[kSimWaves];
   __shared__ int sh_j1;
 
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
-  uint32_t *Mw = Mw_all[wv];
-  const char *Mb = reinterpret_cast<const char *>(Mw);
+  uint32_t *Mx = reinterpret_cast<uint32_t *>(Mw2[wv]);
+  const char *Mb = reinterpret_cast<const char *>(&Mw2[0][0]);
 
   for (int64_t item = blockIdx.x; item < a.n_items; item += gridDim.x) {
     const SimItem it = a.items[item];
@@ -333,8 +333,8 @@ __global__ __launch_bounds__(kSimThreads, 4) void sim_kernel(SimArgs a) {
       }
       const int nlid = total + 1;
       // every wave's mask words start at zero; each source sentence clears what it set
-      for (int k = tid; k < kSimWaves * (kTcap + 4) / 4; k += kSimThreads)
-        reinterpret_cast<uint4 *>(&Mw_all[0][0])[k] = make_uint4(0, 0, 0, 0);
+      for (int k = tid; k < kSimWaves * (kTcap + 4) / 2; k += kSimThreads)
+        reinterpret_cast<uint4 *>(&Mw2[0][0])[k] = make_uint4(0, 0, 0, 0);
       __syncthreads();
       for (int q = tid; q < npad; q += kSimThreads) {
         const uint16_t s = tdoc[q];
@@ -342,179 +342,209 @@ __global__ __launch_bounds__(kSimThreads, 4) void sim_kernel(SimArgs a) {
       }
       __syncthreads();
 
-      // this lane's target sentence and its word addresses
+      // this lane's target sentence and the LDS byte offsets of its mask
+      // entries (from the block's first entry; 8 bytes per local id)
       const bool jok = lane < nj;
       const int bl = jok ? tlen[lane] : 0;
       const uint16_t *tp = tdoc + (jok ? toff[lane] : 0);
+      const uint32_t wbase = (uint32_t)wv * (kTcap + 4) * 8u;
       uint32_t ad[kRegTok];
 #pragma unroll
-      for (int k = 0; k < kRegTok; k++) ad[k] = k < bl ? (uint32_t)tp[k] << 2 : 0u;
+      for (int k = 0; k < kRegTok; k++) ad[k] = wbase + (k < bl ? (uint32_t)tp[k] * 8u : 0u);
       const int maxb = __builtin_amdgcn_readfirstlane(wave_max(bl));
       const int ng = (min(maxb, kRegTok) + 3) >> 2;
-      const int nq4 = (nlid + 3) >> 2;
+      const int nq4 = (nlid + 1) >> 1;  // 16-byte stores covering the chunk's entries
 
-      // Row k of this wave is source sentence i = i0 + wv + 4k; lane k holds
-      // its token range.  The translations of row k + 1 (positions < 64) are
-      // fetched while row k is worked on (two register sets, no copy), and a
-      // row's scores are stored while the next row is worked on.
-      auto fetch = [&](int k) -> int4 {
-        if (k >= nrows) return make_int4(-1, -1, -1, -1);
-        const int64_t b0 = readlane64(rsb, k);
-        const int len = __builtin_amdgcn_readlane(rlen, k);
-        return lane < len ? a.trans[b0 + lane] : make_int4(-1, -1, -1, -1);
+      // Score of cell (i, j0 + lane) from its counts; stored one call later
+      // (two pending slots, one per half), so the table read is not waited
+      // for before the next rows' work.
+      float *pend_dst0 = nullptr, *pend_dst1 = nullptr;
+      float pend_sv0 = 0.0f, pend_sv1 = 0.0f;
+      auto score_cell = [&](int i, int ai, uint32_t ms, uint32_t mt, float *&dst) -> float {
+        dst = nullptr;
+        if (!jok) return 0.0f;
+        const float sv = (ai < kTabLen && bl < kTabLen)
+                             ? a.table[((ai * kTabLen + bl) * kTabLen + (int)ms) * kTabLen + (int)mt]
+                             : score_direct(a.w0, a.w1, a.w2, a.w3, (int)ms, ai, (int)mt, bl);
+        dst = a.S + d.s_off + score_pos(i, j0 + lane, n, m);
+        if (a.ms_out) {
+          const int64_t cell = d.rm_off + (int64_t)i * m + j0 + lane;
+          a.ms_out[cell] = (int)ms;
+          a.mt_out[cell] = (int)mt;
+        }
+        return sv;
       };
-      float *pend_dst = nullptr;
-      float pend_sv = 0.0f;
-      auto row = [&](const int k, const int4 cur) {
+
+      // One row at a time (sentences of more than 31 tokens): lane q holds
+      // source position q < 64; the mask uses the first word of each entry.
+      auto single_row = [&](const int k) {
         const int i = it.i0 + wv + kSimWaves * k;
         const int64_t sb = readlane64(rsb, k);
         const int ai = __builtin_amdgcn_readlane(rlen, k);
+        const int4 cur = lane < ai ? a.trans[sb + lane] : make_int4(-1, -1, -1, -1);
         uint32_t ms_acc = 0, mt_acc = 0;
-        if (ai <= 64) {
-          // one token per lane: its (at most four) local ids stay in registers
-          // and only those words are cleared afterwards
-          const bool far = cur.x == -2;  // more than four translations
-          int l0 = 0, l1 = 0, l2 = 0, l3 = 0;
-          if (!far) {
-            l0 = u2_lid(uent, cur.x);
-            l1 = u2_lid(uent, cur.y);
-            l2 = u2_lid(uent, cur.z);
-            l3 = u2_lid(uent, cur.w);
-          }
-          const int npass = ai <= kPosBits ? 1 : (ai + kPosBits - 1) / kPosBits;
-          for (int c = 0; c < npass; c++) {
-            const int rel = lane - kPosBits * c;
+        const int npass = ai <= kPosBits ? 1 : (ai + kPosBits - 1) / kPosBits;
+        for (int c = 0; c < npass; c++) {
+          const int qlo = c == 0 ? 0 : kPosBits * c;
+          const int qhi = c == 0 ? ai : min(ai, kPosBits * c + kPosBits);
+          for (int q = qlo + lane; q < qhi; q += 64) {
+            const int4 t4 = (c == 0 && q < 64) ? cur : a.trans[sb + q];  // cur holds position `lane`
+            const int rel = q - kPosBits * c;
             const uint32_t bits = (c == 0 ? kHitBit : 0u) | (rel >= 0 && rel < kPosBits ? (1u << rel) : 0u);
-            if (lane < ai && bits) {
-              if (far) {
-                for (int e = 0; e < cur.z; e++) {
-                  const int l = u2_lid(uent, a.lex.vals[cur.y + e]);
-                  if (l) atomicOr(&Mw[l], bits);
-                }
-              } else {
-                if (l0) atomicOr(&Mw[l0], bits);
-                if (l1) atomicOr(&Mw[l1], bits);
-                if (l2) atomicOr(&Mw[l2], bits);
-                if (l3) atomicOr(&Mw[l3], bits);
+            if (t4.x == -2) {
+              for (int e = 0; e < t4.z; e++) {
+                const int l = u2_lid(uent, a.lex.vals[t4.y + e]);
+                if (l) atomicOr(&Mx[2 * l], bits);
               }
+            } else {
+              const int l0 = u2_lid(uent, t4.x), l1 = u2_lid(uent, t4.y), l2 = u2_lid(uent, t4.z),
+                        l3 = u2_lid(uent, t4.w);
+              if (l0) atomicOr(&Mx[2 * l0], bits);
+              if (l1) atomicOr(&Mx[2 * l1], bits);
+              if (l2) atomicOr(&Mx[2 * l2], bits);
+              if (l3) atomicOr(&Mx[2 * l3], bits);
             }
-            wave_sync();
-            uint32_t acc = 0, mt = 0;
+          }
+          wave_sync();
+          uint32_t acc = 0, mt = 0;
 #pragma unroll
-            for (int g = 0; g < kRegTok / 4; g++) {
-              if (g < ng) {
-                const uint32_t w0 = *reinterpret_cast<const uint32_t *>(Mb + ad[4 * g]);
-                const uint32_t w1 = *reinterpret_cast<const uint32_t *>(Mb + ad[4 * g + 1]);
-                const uint32_t w2 = *reinterpret_cast<const uint32_t *>(Mb + ad[4 * g + 2]);
-                const uint32_t w3 = *reinterpret_cast<const uint32_t *>(Mb + ad[4 * g + 3]);
-                mt += ((w0 >> 31) + (w1 >> 31)) + ((w2 >> 31) + (w3 >> 31));
-                acc |= (w0 | w1) | (w2 | w3);
-              }
+          for (int g = 0; g < kRegTok / 4; g++) {
+            if (g < ng) {
+              const uint32_t w0 = *reinterpret_cast<const uint32_t *>(Mb + ad[4 * g]);
+              const uint32_t w1 = *reinterpret_cast<const uint32_t *>(Mb + ad[4 * g + 1]);
+              const uint32_t w2 = *reinterpret_cast<const uint32_t *>(Mb + ad[4 * g + 2]);
+              const uint32_t w3 = *reinterpret_cast<const uint32_t *>(Mb + ad[4 * g + 3]);
+              mt += ((w0 >> 31) + (w1 >> 31)) + ((w2 >> 31) + (w3 >> 31));
+              acc |= (w0 | w1) | (w2 | w3);
             }
-            if (maxb > kRegTok) {  // sentences beyond 32 tokens: the rest straight from LDS
-              for (int k = kRegTok; k < bl; k++) {
-                const uint32_t w = Mw[tp[k]];
-                mt += w >> 31;
-                acc |= w;
-              }
-            }
-            ms_acc += __popc(acc & ~kHitBit);
-            if (c == 0) mt_acc = mt;
-            wave_sync();
-            if (lane < ai) {
-              if (far) {
-                for (int e = 0; e < cur.z; e++) {
-                  const int l = u2_lid(uent, a.lex.vals[cur.y + e]);
-                  if (l) Mw[l] = 0;
-                }
-              } else {
-                if (l0) Mw[l0] = 0;
-                if (l1) Mw[l1] = 0;
-                if (l2) Mw[l2] = 0;
-                if (l3) Mw[l3] = 0;
-              }
-            }
-            wave_sync();
           }
-        } else {
-          // long source sentence: several positions per lane, whole mask cleared per pass
-          const int npass = (ai + kPosBits - 1) / kPosBits;
-          for (int c = 0; c < npass; c++) {
-            const int qlo = c == 0 ? 0 : kPosBits * c;
-            const int qhi = c == 0 ? ai : min(ai, kPosBits * c + kPosBits);
-            for (int q = qlo + lane; q < qhi; q += 64) {
-              const int4 t4 = (c == 0 && q < 64) ? cur : a.trans[sb + q];  // cur holds position `lane`
-              const int rel = q - kPosBits * c;
-              const uint32_t bits = (c == 0 ? kHitBit : 0u) | (rel >= 0 && rel < kPosBits ? (1u << rel) : 0u);
-              if (t4.x == -2) {
-                for (int e = 0; e < t4.z; e++) {
-                  const int l = u2_lid(uent, a.lex.vals[t4.y + e]);
-                  if (l) atomicOr(&Mw[l], bits);
-                }
-              } else {
-                const int l0 = u2_lid(uent, t4.x), l1 = u2_lid(uent, t4.y), l2 = u2_lid(uent, t4.z),
-                          l3 = u2_lid(uent, t4.w);
-                if (l0) atomicOr(&Mw[l0], bits);
-                if (l1) atomicOr(&Mw[l1], bits);
-                if (l2) atomicOr(&Mw[l2], bits);
-                if (l3) atomicOr(&Mw[l3], bits);
-              }
+          if (maxb > kRegTok) {  // sentences beyond 32 tokens: the rest straight from LDS
+            for (int k2 = kRegTok; k2 < bl; k2++) {
+              const uint32_t w = Mx[2 * tp[k2]];
+              mt += w >> 31;
+              acc |= w;
             }
-            wave_sync();
-            uint32_t acc = 0, mt = 0;
-#pragma unroll
-            for (int g = 0; g < kRegTok / 4; g++) {
-              if (g < ng) {
-                const uint32_t w0 = *reinterpret_cast<const uint32_t *>(Mb + ad[4 * g]);
-                const uint32_t w1 = *reinterpret_cast<const uint32_t *>(Mb + ad[4 * g + 1]);
-                const uint32_t w2 = *reinterpret_cast<const uint32_t *>(Mb + ad[4 * g + 2]);
-                const uint32_t w3 = *reinterpret_cast<const uint32_t *>(Mb + ad[4 * g + 3]);
-                mt += ((w0 >> 31) + (w1 >> 31)) + ((w2 >> 31) + (w3 >> 31));
-                acc |= (w0 | w1) | (w2 | w3);
-              }
-            }
-            if (maxb > kRegTok) {
-              for (int k = kRegTok; k < bl; k++) {
-                const uint32_t w = Mw[tp[k]];
-                mt += w >> 31;
-                acc |= w;
-              }
-            }
-            ms_acc += __popc(acc & ~kHitBit);
-            if (c == 0) mt_acc = mt;
-            wave_sync();
-            for (int k = lane; k < nq4; k += 64) reinterpret_cast<uint4 *>(Mw)[k] = make_uint4(0, 0, 0, 0);
-            wave_sync();
           }
+          ms_acc += __popc(acc & ~kHitBit);
+          if (c == 0) mt_acc = mt;
+          wave_sync();
+          for (int k2 = lane; k2 < nq4; k2 += 64) reinterpret_cast<uint4 *>(Mx)[k2] = make_uint4(0, 0, 0, 0);
+          wave_sync();
         }
-        // The score is stored one source sentence later, so the table read
-        // is not waited for before the next sentence's work.
-        float sv = 0.0f;
-        float *dst = nullptr;
-        if (jok) {
-          const int ms = (int)ms_acc, mt = (int)mt_acc;
-          sv = (ai < kTabLen && bl < kTabLen) ? a.table[((ai * kTabLen + bl) * kTabLen + ms) * kTabLen + mt]
-                                              : score_direct(a.w0, a.w1, a.w2, a.w3, ms, ai, mt, bl);
-          dst = a.S + d.s_off + score_pos(i, j0 + lane, n, m);
-          if (a.ms_out) {
-            const int64_t cell = d.rm_off + (int64_t)i * m + j0 + lane;
-            a.ms_out[cell] = ms;
-            a.mt_out[cell] = mt;
-          }
-        }
-        if (pend_dst) *pend_dst = pend_sv;
-        pend_dst = dst;
-        pend_sv = sv;
+        float *dst;
+        const float sv = score_cell(i, ai, ms_acc, mt_acc, dst);
+        if (dst) *dst = sv;
       };
-      int4 bufA = fetch(0), bufB;
-      for (int k = 0; k < nrows; k += 2) {
-        bufB = fetch(k + 1);
-        row(k, bufA);
-        if (k + 1 >= nrows) break;
-        bufA = fetch(k + 2);
-        row(k + 1, bufB);
+
+      // Two rows at a time (both of at most 31 tokens): lanes 0-31 hold the
+      // positions of row k, lanes 32-63 those of row k + 1; row k marks the
+      // first word of each entry and row k + 1 the second, so one 8-byte read
+      // per target token serves both rows.  The translations of the next two
+      // rows are fetched while these are worked on.
+      auto fetch2 = [&](int k) -> int4 {
+        const int64_t b0 = readlane64(rsb, min(k, 31)), b1 = readlane64(rsb, min(k + 1, 31));
+        const int n0 = k < nrows ? __builtin_amdgcn_readlane(rlen, min(k, 31)) : 0;
+        const int n1 = k + 1 < nrows ? __builtin_amdgcn_readlane(rlen, min(k + 1, 31)) : 0;
+        const int q = lane & 31, len = lane < 32 ? n0 : n1;
+        const bool ok = q < len && len <= kPosBits;
+        return ok ? a.trans[(lane < 32 ? b0 : b1) + q] : make_int4(-1, -1, -1, -1);
+      };
+      auto pair_rows = [&](const int k, const int4 cur) {
+        const int ai0 = __builtin_amdgcn_readlane(rlen, k);
+        const bool has1 = k + 1 < nrows;
+        const int ai1 = has1 ? __builtin_amdgcn_readlane(rlen, k + 1) : 0;
+        if (ai0 > kPosBits || ai1 > kPosBits) {
+          single_row(k);
+          if (has1) single_row(k + 1);
+          return;
+        }
+        const int half = lane >> 5, q = lane & 31;
+        const int aih = half ? ai1 : ai0;
+        const bool mine = q < aih;
+        const bool far = cur.x == -2;  // more than four translations
+        int l0 = 0, l1 = 0, l2 = 0, l3 = 0;
+        if (!far) {
+          l0 = u2_lid(uent, cur.x);
+          l1 = u2_lid(uent, cur.y);
+          l2 = u2_lid(uent, cur.z);
+          l3 = u2_lid(uent, cur.w);
+        }
+        uint32_t *Mh = Mx + half;  // this half's word of entry l: Mh[2 l]
+        const uint32_t bits = kHitBit | (1u << q);
+        if (mine) {
+          if (far) {
+            for (int e = 0; e < cur.z; e++) {
+              const int l = u2_lid(uent, a.lex.vals[cur.y + e]);
+              if (l) atomicOr(&Mh[2 * l], bits);
+            }
+          } else {
+            if (l0) atomicOr(&Mh[2 * l0], bits);
+            if (l1) atomicOr(&Mh[2 * l1], bits);
+            if (l2) atomicOr(&Mh[2 * l2], bits);
+            if (l3) atomicOr(&Mh[2 * l3], bits);
+          }
+        }
+        wave_sync();
+        uint32_t acc0 = 0, mt0 = 0, acc1 = 0, mt1 = 0;
+#pragma unroll
+        for (int g = 0; g < kRegTok / 4; g++) {
+          if (g < ng) {
+            const uint2 w0 = *reinterpret_cast<const uint2 *>(Mb + ad[4 * g]);
+            const uint2 w1 = *reinterpret_cast<const uint2 *>(Mb + ad[4 * g + 1]);
+            const uint2 w2 = *reinterpret_cast<const uint2 *>(Mb + ad[4 * g + 2]);
+            const uint2 w3 = *reinterpret_cast<const uint2 *>(Mb + ad[4 * g + 3]);
+            mt0 += ((w0.x >> 31) + (w1.x >> 31)) + ((w2.x >> 31) + (w3.x >> 31));
+            acc0 |= (w0.x | w1.x) | (w2.x | w3.x);
+            mt1 += ((w0.y >> 31) + (w1.y >> 31)) + ((w2.y >> 31) + (w3.y >> 31));
+            acc1 |= (w0.y | w1.y) | (w2.y | w3.y);
+          }
+        }
+        if (maxb > kRegTok) {
+          for (int k2 = kRegTok; k2 < bl; k2++) {
+            const uint2 w = *reinterpret_cast<const uint2 *>(Mx + 2 * tp[k2]);
+            mt0 += w.x >> 31;
+            acc0 |= w.x;
+            mt1 += w.y >> 31;
+            acc1 |= w.y;
+          }
+        }
+        wave_sync();
+        if (mine) {
+          if (far) {
+            for (int e = 0; e < cur.z; e++) {
+              const int l = u2_lid(uent, a.lex.vals[cur.y + e]);
+              if (l) Mh[2 * l] = 0;
+            }
+          } else {
+            if (l0) Mh[2 * l0] = 0;
+            if (l1) Mh[2 * l1] = 0;
+            if (l2) Mh[2 * l2] = 0;
+            if (l3) Mh[2 * l3] = 0;
+          }
+        }
+        wave_sync();
+        const int i = it.i0 + wv + kSimWaves * k;
+        float *dst0, *dst1 = nullptr;
+        const float sv0 = score_cell(i, ai0, __popc(acc0 & ~kHitBit), mt0, dst0);
+        float sv1 = 0.0f;
+        if (has1) sv1 = score_cell(i + kSimWaves, ai1, __popc(acc1 & ~kHitBit), mt1, dst1);
+        if (pend_dst0) *pend_dst0 = pend_sv0;
+        if (pend_dst1) *pend_dst1 = pend_sv1;
+        pend_dst0 = dst0;
+        pend_sv0 = sv0;
+        pend_dst1 = dst1;
+        pend_sv1 = sv1;
+      };
+      int4 bufA = fetch2(0), bufB;
+      for (int k = 0; k < nrows; k += 4) {
+        bufB = fetch2(k + 2);
+        pair_rows(k, bufA);
+        if (k + 2 >= nrows) break;
+        bufA = fetch2(k + 4);
+        pair_rows(k + 2, bufB);
       }
-      if (pend_dst) *pend_dst = pend_sv;
+      if (pend_dst0) *pend_dst0 = pend_sv0;
+      if (pend_dst1) *pend_dst1 = pend_sv1;
       __syncthreads();
       j0 = j1;
     }
