@@ -65,51 +65,58 @@ __global__ __launch_bounds__(256) void score_table_kernel(float w0, float w1, fl
 }
 
 // ---------------------------------------------------------------- lexicon
+// Lexicon slot h is two int4: {key, count, offset, -1} and the key's
+// translation record: up to four target ids inline (-1 padded), or
+// {-2, offset, count, 0} for a key with more than four (read from the value
+// array when used).
 __global__ __launch_bounds__(256) void lex_insert_kernel(const int32_t *keys, const int32_t *cnts,
-                                                         const int64_t *offs, int64_t n, int4 *slots,
-                                                         uint32_t mask, int shift) {
+                                                         const int64_t *offs, const int32_t *vals, int64_t n,
+                                                         int4 *slots, uint32_t mask, int shift) {
   const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (k >= n) return;
   const int32_t key = keys[k];
   uint32_t h = hash32(key) >> shift;
   for (;;) {  // load factor <= 1/2 and distinct keys: an empty slot is always reached
-    const int prev = atomicCAS(&slots[h].x, kEmpty, key);
+    const int prev = atomicCAS(&slots[2 * h].x, kEmpty, key);
     if (prev == kEmpty) {
-      slots[h].y = cnts[k];
-      slots[h].z = (int32_t)offs[k];
+      const int c = cnts[k];
+      const int32_t o = (int32_t)offs[k];
+      slots[2 * h].y = c;
+      slots[2 * h].z = o;
+      int4 r = make_int4(-1, -1, -1, -1);
+      if (c > 4) {
+        r = make_int4(-2, o, c, 0);
+      } else {
+        if (c > 0) r.x = vals[o];
+        if (c > 1) r.y = vals[o + 1];
+        if (c > 2) r.z = vals[o + 2];
+        if (c > 3) r.w = vals[o + 3];
+      }
+      slots[2 * h + 1] = r;
       return;
     }
     h = (h + 1) & mask;
   }
 }
 
-// {offset, count} of T(x) in the value array; count 0 when x is not a key.
-__device__ __forceinline__ int2 lex_find(const LexDev &L, int32_t x) {
-  if (x < 0) return make_int2(0, 0);
-  uint32_t h = hash32(x) >> L.shift;
-  for (;;) {
-    const int4 s = L.slots[h];
-    if (s.x == x) return make_int2(s.z, s.y);
-    if (s.x == kEmpty) return make_int2(0, 0);
-    h = (h + 1) & L.mask;
-  }
-}
-
-// Translations of every source token of a batch, resolved once per call:
-// up to four target ids inline (-1 padded), or {-2, offset, count, 0} for a
-// key with more than four (read from the value array when used).
+// Translations of every source token of a batch, resolved once per call
+// (the slot's record; -1 x 4 for ids that are not keys).
 __global__ __launch_bounds__(256) void translate_kernel(const int32_t *tok, int64_t n, LexDev L, int4 *out) {
   const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (k >= n) return;
-  const int2 oc = lex_find(L, tok[k]);
+  const int32_t x = tok[k];
   int4 r = make_int4(-1, -1, -1, -1);
-  if (oc.y > 4) {
-    r = make_int4(-2, oc.x, oc.y, 0);
-  } else {
-    if (oc.y > 0) r.x = L.vals[oc.x];
-    if (oc.y > 1) r.y = L.vals[oc.x + 1];
-    if (oc.y > 2) r.z = L.vals[oc.x + 2];
-    if (oc.y > 3) r.w = L.vals[oc.x + 3];
+  if (x >= 0) {
+    uint32_t h = hash32(x) >> L.shift;
+    for (;;) {
+      const int4 s = L.slots[2 * h], t = L.slots[2 * h + 1];
+      if (s.x == x) {
+        r = t;
+        break;
+      }
+      if (s.x == kEmpty) break;
+      h = (h + 1) & L.mask;
+    }
   }
   out[k] = r;
 }
@@ -229,6 +236,40 @@ __device__ __forceinline__ int u2_lid(const int2 *ent, int32_t x) {
     e = ent[h];
   }
   return e.x == x ? e.y : 0;
+}
+
+// local ids of four keys at once: the four first probes are issued together
+__device__ __forceinline__ int4 u2_lid4(const int2 *ent, const int4 x) {
+  constexpr uint32_t kMask = kUcap - 1;
+  uint32_t h0 = hash32(x.x) >> (32 - kLogUcap), h1 = hash32(x.y) >> (32 - kLogUcap);
+  uint32_t h2 = hash32(x.z) >> (32 - kLogUcap), h3 = hash32(x.w) >> (32 - kLogUcap);
+  int2 e0 = ent[h0], e1 = ent[h1], e2 = ent[h2], e3 = ent[h3];
+  bool p0 = x.x >= 0 && e0.x != x.x && e0.x != kEmpty, p1 = x.y >= 0 && e1.x != x.y && e1.x != kEmpty;
+  bool p2 = x.z >= 0 && e2.x != x.z && e2.x != kEmpty, p3 = x.w >= 0 && e3.x != x.w && e3.x != kEmpty;
+  while (p0 || p1 || p2 || p3) {
+    if (p0) {
+      h0 = (h0 + 1) & kMask;
+      e0 = ent[h0];
+      p0 = e0.x != x.x && e0.x != kEmpty;
+    }
+    if (p1) {
+      h1 = (h1 + 1) & kMask;
+      e1 = ent[h1];
+      p1 = e1.x != x.y && e1.x != kEmpty;
+    }
+    if (p2) {
+      h2 = (h2 + 1) & kMask;
+      e2 = ent[h2];
+      p2 = e2.x != x.z && e2.x != kEmpty;
+    }
+    if (p3) {
+      h3 = (h3 + 1) & kMask;
+      e3 = ent[h3];
+      p3 = e3.x != x.w && e3.x != kEmpty;
+    }
+  }
+  return make_int4(x.x >= 0 && e0.x == x.x ? e0.y : 0, x.y >= 0 && e1.x == x.y ? e1.y : 0,
+                   x.z >= 0 && e2.x == x.z ? e2.y : 0, x.w >= 0 && e3.x == x.w ? e3.y : 0);
 }
 
 __device__ __forceinline__ int64_t readlane64(int64_t v, int k) {
@@ -462,13 +503,8 @@ __global__ __launch_bounds__(kSimThreads, 3) void sim_kernel(SimArgs a) {
         const int aih = half ? ai1 : ai0;
         const bool mine = q < aih;
         const bool far = cur.x == -2;  // more than four translations
-        int l0 = 0, l1 = 0, l2 = 0, l3 = 0;
-        if (!far) {
-          l0 = u2_lid(uent, cur.x);
-          l1 = u2_lid(uent, cur.y);
-          l2 = u2_lid(uent, cur.z);
-          l3 = u2_lid(uent, cur.w);
-        }
+        const int4 lid = u2_lid4(uent, far ? make_int4(-1, -1, -1, -1) : cur);
+        const int l0 = lid.x, l1 = lid.y, l2 = lid.z, l3 = lid.w;
         uint32_t *Mh = Mx + half;  // this half's word of entry l: Mh[2 l]
         const uint32_t bits = kHitBit | (1u << q);
         if (mine) {
@@ -485,18 +521,21 @@ __global__ __launch_bounds__(kSimThreads, 3) void sim_kernel(SimArgs a) {
           }
         }
         wave_sync();
+        // eight entries per batch (entries past a sentence's end are entry 0, always zero)
         uint32_t acc0 = 0, mt0 = 0, acc1 = 0, mt1 = 0;
 #pragma unroll
-        for (int g = 0; g < kRegTok / 4; g++) {
-          if (g < ng) {
-            const uint2 w0 = *reinterpret_cast<const uint2 *>(Mb + ad[4 * g]);
-            const uint2 w1 = *reinterpret_cast<const uint2 *>(Mb + ad[4 * g + 1]);
-            const uint2 w2 = *reinterpret_cast<const uint2 *>(Mb + ad[4 * g + 2]);
-            const uint2 w3 = *reinterpret_cast<const uint2 *>(Mb + ad[4 * g + 3]);
-            mt0 += ((w0.x >> 31) + (w1.x >> 31)) + ((w2.x >> 31) + (w3.x >> 31));
-            acc0 |= (w0.x | w1.x) | (w2.x | w3.x);
-            mt1 += ((w0.y >> 31) + (w1.y >> 31)) + ((w2.y >> 31) + (w3.y >> 31));
-            acc1 |= (w0.y | w1.y) | (w2.y | w3.y);
+        for (int g = 0; g < kRegTok / 8; g++) {
+          if (2 * g < ng) {
+            uint2 w[8];
+#pragma unroll
+            for (int u = 0; u < 8; u++) w[u] = *reinterpret_cast<const uint2 *>(Mb + ad[8 * g + u]);
+#pragma unroll
+            for (int u = 0; u < 8; u += 4) {
+              mt0 += ((w[u].x >> 31) + (w[u + 1].x >> 31)) + ((w[u + 2].x >> 31) + (w[u + 3].x >> 31));
+              acc0 |= (w[u].x | w[u + 1].x) | (w[u + 2].x | w[u + 3].x);
+              mt1 += ((w[u].y >> 31) + (w[u + 1].y >> 31)) + ((w[u + 2].y >> 31) + (w[u + 3].y >> 31));
+              acc1 |= (w[u].y | w[u + 1].y) | (w[u + 2].y | w[u + 3].y);
+            }
           }
         }
         if (maxb > kRegTok) {
@@ -1396,11 +1435,11 @@ __global__ void fill_i32_kernel(int32_t *p, int32_t v, int64_t n) {
 }
 
 // --------------------------------------------------------------- launches
-hipError_t launch_lex_insert(const int32_t *keys, const int32_t *cnts, const int64_t *offs, int64_t n, int4 *slots,
-                             uint32_t mask, int shift, hipStream_t st) {
+hipError_t launch_lex_insert(const int32_t *keys, const int32_t *cnts, const int64_t *offs, const int32_t *vals,
+                             int64_t n, int4 *slots, uint32_t mask, int shift, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(lex_insert_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, keys, cnts, offs, n,
-                     slots, mask, shift);
+  hipLaunchKernelGGL(lex_insert_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, keys, cnts, offs, vals,
+                     n, slots, mask, shift);
   return hipGetLastError();
 }
 

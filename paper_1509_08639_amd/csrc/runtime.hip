@@ -346,7 +346,7 @@ ym_status ym_lexicon_load(ym_ctx *c, const int32_t *src_ids, const int64_t *off,
     if (dcnts) hipFree(dcnts);
     if (doffs) hipFree(doffs);
   };
-  if ((e = hipMalloc(&L->slots, (size_t)cap * sizeof(int4))) != hipSuccess ||
+  if ((e = hipMalloc(&L->slots, (size_t)cap * 2 * sizeof(int4))) != hipSuccess ||
       (e = hipMalloc(&L->vals, std::max<size_t>(vals.size(), 1) * 4)) != hipSuccess ||
       (e = hipMalloc(&dkeys, std::max<size_t>(keys.size(), 1) * 4)) != hipSuccess ||
       (e = hipMalloc(&dcnts, std::max<size_t>(keys.size(), 1) * 4)) != hipSuccess ||
@@ -358,15 +358,15 @@ ym_status ym_lexicon_load(ym_ctx *c, const int32_t *src_ids, const int64_t *off,
     delete L;
     return fail(YM_ENOMEM, "device memory for lexicon");
   }
-  e = hipMemsetAsync(L->slots, 0xFF, (size_t)cap * sizeof(int4), c->stream);  // keys = -1 (empty)
+  e = hipMemsetAsync(L->slots, 0xFF, (size_t)cap * 2 * sizeof(int4), c->stream);  // keys = -1 (empty)
   if (e == hipSuccess && !vals.empty())
     e = hipMemcpyAsync(L->vals, vals.data(), vals.size() * 4, hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess && !keys.empty()) e = hipMemcpyAsync(dkeys, keys.data(), keys.size() * 4, hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess && !keys.empty()) e = hipMemcpyAsync(dcnts, cnts.data(), keys.size() * 4, hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess && !keys.empty()) e = hipMemcpyAsync(doffs, offs.data(), keys.size() * 8, hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess)
-    e = launch_lex_insert((const int32_t *)dkeys, (const int32_t *)dcnts, (const int64_t *)doffs, (int64_t)keys.size(),
-                          L->slots, L->mask, L->shift, c->stream);
+    e = launch_lex_insert((const int32_t *)dkeys, (const int32_t *)dcnts, (const int64_t *)doffs, L->vals,
+                          (int64_t)keys.size(), L->slots, L->mask, L->shift, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   cleanup();
   if (e != hipSuccess) {

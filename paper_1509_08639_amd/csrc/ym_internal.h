@@ -68,7 +68,7 @@ struct SimItem {
 // Lexicon as resident in HBM: open-addressing table of {key, count, offset, 0}
 // slots (linear probing, load <= 1/2) over a CSR value array.
 struct LexDev {
-  const int4 *slots;
+  const int4 *slots;  // two int4 per slot: {key, count, offset, -1}, translation record
   const int32_t *vals;
   uint32_t mask;
   int32_t shift;
@@ -110,8 +110,8 @@ struct NwArgs {
 };
 
 // Launch wrappers (kernels.hip).
-hipError_t launch_lex_insert(const int32_t *keys, const int32_t *cnts, const int64_t *offs, int64_t n, int4 *slots,
-                             uint32_t mask, int shift, hipStream_t st);
+hipError_t launch_lex_insert(const int32_t *keys, const int32_t *cnts, const int64_t *offs, const int32_t *vals,
+                             int64_t n, int4 *slots, uint32_t mask, int shift, hipStream_t st);
 hipError_t launch_translate(const int32_t *tok, int64_t n, const LexDev &L, int4 *out, hipStream_t st);
 hipError_t launch_score_table(float w0, float w1, float w2, float w3, float *table, hipStream_t st);
 // variant 0: bit-sliced tile kernel; 1: lane-per-target-sentence kernel
