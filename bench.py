@@ -32,6 +32,26 @@ CUS, CLOCK_GHZ, LANES = 256, 2.4, 64
 ALU_PEAK_TOPS = CUS * LANES * CLOCK_GHZ * 1e9 / 1e12  # 32-bit VALU lane operations per second (non-packed)
 
 
+def profiled_traffic(kernel, workload_name):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, copy-calibrated), or None when the
+    summary is for another workload or the kernel source has changed since."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload_name}.md")
+    src = os.path.join(ROOT, "paper_1509_08639_amd", "csrc", "kernels.hip")
+    try:
+        text = open(path).read()
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    m = re.search(r"traffic_bytes " + re.escape(kernel) + r": (\d+)", text)
+    h = re.search(r"sha256\s+([0-9a-f]{64})", text)
+    if not m or not h or h.group(1) != sha:
+        return None
+    return int(m.group(1))
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -256,12 +276,12 @@ def main():
     if sim_ms >= nw_ms:
         ach = kern["similarity"]["achieved_TOPs"]
         roof = dict(kernel="similarity", bound="alu", achieved=ach, peak=ALU_PEAK_TOPS, unit="TOP/s",
-                    frac=ach / ALU_PEAK_TOPS, traffic=None,
+                    frac=ach / ALU_PEAK_TOPS, traffic=profiled_traffic("sim_kernel", cfg.name),
                     per_unit=f"{sim_ops_per_cell:.2f} ops/cell (mean b + mean k*a + 20)")
     else:
         ach = kern["nw"]["achieved_GBs"]
         roof = dict(kernel="nw", bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
-                    traffic=None, per_unit="4.25 B/cell")
+                    traffic=profiled_traffic("nw_kernel", cfg.name), per_unit="4.25 B/cell")
 
     # plain per-pair GPU form vs the batched form on the same pairs (host entry points, both
     # copy inputs in and results out)
