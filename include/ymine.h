@@ -238,6 +238,31 @@ ym_status ym_tune(ym_ctx *ctx, const ym_lexicon *lex, const ym_batch *batch, con
 ym_status ym_mine_bidirectional(ym_ctx *ctx, const ym_lexicon *lex_fwd, const ym_lexicon *lex_rev,
                                 const ym_batch *batch, const ym_params *fwd, const ym_params *rev, ym_result **out);
 
+/* ------------------------------------------------------------ launch tuning */
+
+/* Launch configuration of a context (applies to every entry point; set it
+ * before starting a server on the context).  None of these choices changes a
+ * result: they only change how work is split over workgroups. */
+typedef struct {
+  int32_t sim_kernel;         /* similarity kernel: 1 one lane per target sentence (default), 0 bit-sliced tiles */
+  int32_t item_rows;          /* source sentences per similarity work item: 64, 128 (default) or 256 */
+  int32_t nw_pairs_per_group; /* document pairs per NW workgroup, one wave each: 1 (default), 2 or 4 */
+} ym_tuning;
+
+/* Set / read the configuration.  YM_EINVAL for values outside the lists above. */
+ym_status ym_set_tuning(ym_ctx *ctx, const ym_tuning *tuning);
+ym_status ym_get_tuning(ym_ctx *ctx, ym_tuning *tuning);
+
+/* Autotuner: times the whole path (similarity, NW, compaction) on `sample`
+ * with HIP events on the context's stream, `reps` timed passes per candidate
+ * after one untimed pass, first over the six (sim_kernel, item_rows) pairs and
+ * then over the NW workgroup sizes with the best of them.  The fastest
+ * configuration is applied to the context and returned in *best, its mean
+ * time per pass in *best_ms (may be NULL).  On error the previous
+ * configuration is kept. */
+ym_status ym_autotune(ym_ctx *ctx, const ym_lexicon *lex, const ym_batch *sample, const ym_params *params,
+                      int32_t reps, ym_tuning *best, double *best_ms);
+
 /* ------------------------------------------------------------ kernel timing */
 
 /* Record HIP events around every kernel the context launches (on the stream

@@ -208,7 +208,7 @@ ym_status mine_host(ym_ctx *c, const ym_lexicon *L, const ym_batch *b, const ym_
   size_t need = 0;
   std::vector<Chunk> lay(chunks.size());
   for (size_t k = 0; k < chunks.size(); k++) {
-    lay[k].layout(b->src_doc_off, b->tgt_doc_off, chunks[k].first, chunks[k].second);
+    lay[k].layout(b->src_doc_off, b->tgt_doc_off, chunks[k].first, chunks[k].second, c->item_rows);
     need = std::max(need, lay[k].bytes);
   }
   if ((s = c->ws.reserve(head + std::max<size_t>(need, 256)))) {
@@ -328,7 +328,7 @@ ym_status ym_mine_device(ym_ctx *c, const ym_lexicon *L, const ym_device_batch *
   if ((s = translate_batch(c, L, d, (char *)workspace, st))) return s;
   for (auto &ck : chunks) {
     Chunk ch;
-    ch.layout(b->src_doc_off, b->tgt_doc_off, ck.first, ck.second);
+    ch.layout(b->src_doc_off, b->tgt_doc_off, ck.first, ck.second, c->item_rows);
     if (ch.bytes > workspace_bytes - head) return fail(YM_ENOMEM, "workspace too small");
     if ((s = run_chunk(c, L, d, prm, b->src_doc_off, b->tgt_doc_off, ch, (char *)workspace + head, *out, st, nullptr)))
       return s;
@@ -396,7 +396,7 @@ ym_status ym_tune(ym_ctx *c, const ym_lexicon *L, const ym_batch *b, const float
   std::vector<Chunk> lay(chunks.size());
   size_t need = 256;
   for (size_t k = 0; k < chunks.size(); k++) {
-    lay[k].layout(b->src_doc_off, b->tgt_doc_off, chunks[k].first, chunks[k].second);
+    lay[k].layout(b->src_doc_off, b->tgt_doc_off, chunks[k].first, chunks[k].second, c->item_rows);
     need = std::max(need, lay[k].bytes);
   }
   if ((s = c->ws.reserve(head + need))) return s;
@@ -487,7 +487,7 @@ ym_status ym_mine_bidirectional(ym_ctx *c, const ym_lexicon *Lf, const ym_lexico
     std::vector<Chunk> lay(chunks.size());
     size_t need = 256;
     for (size_t k = 0; k < chunks.size(); k++) {
-      lay[k].layout(sdo, tdo, chunks[k].first, chunks[k].second);
+      lay[k].layout(sdo, tdo, chunks[k].first, chunks[k].second, c->item_rows);
       need = std::max(need, lay[k].bytes);
     }
     if ((s = c->ws.reserve(head + need))) return s;
@@ -506,6 +506,134 @@ ym_status ym_mine_bidirectional(ym_ctx *c, const ym_lexicon *Lf, const ym_lexico
   s = download_result(c, P, o, out);
   hipStreamSynchronize(c->stream);
   return s;
+}
+
+// ------------------------------------------------------------ tuning of launches
+static ym_status check_tuning(const ym_tuning *t) {
+  if (!t) return fail(YM_EINVAL, "NULL tuning");
+  if (t->sim_kernel != 0 && t->sim_kernel != 1) return fail(YM_EINVAL, "sim_kernel must be 0 or 1");
+  if (t->item_rows != 64 && t->item_rows != 128 && t->item_rows != 256)
+    return fail(YM_EINVAL, "item_rows must be 64, 128 or 256");
+  if (t->nw_pairs_per_group != 1 && t->nw_pairs_per_group != 2 && t->nw_pairs_per_group != 4)
+    return fail(YM_EINVAL, "nw_pairs_per_group must be 1, 2 or 4");
+  return YM_OK;
+}
+
+static void apply_tuning(ym_ctx *c, const ym_tuning &t) {
+  c->sim_variant = t.sim_kernel;
+  c->item_rows = t.item_rows;
+  c->nw_pairs_per_group = t.nw_pairs_per_group;
+}
+
+ym_status ym_set_tuning(ym_ctx *c, const ym_tuning *t) {
+  if (!c) return fail(YM_EINVAL, "NULL context");
+  ym_status s;
+  if ((s = check_tuning(t))) return s;
+  std::lock_guard<std::mutex> lk(c->mu);
+  apply_tuning(c, *t);
+  return YM_OK;
+}
+
+ym_status ym_get_tuning(ym_ctx *c, ym_tuning *t) {
+  if (!c || !t) return fail(YM_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(c->mu);
+  t->sim_kernel = c->sim_variant;
+  t->item_rows = c->item_rows;
+  t->nw_pairs_per_group = c->nw_pairs_per_group;
+  return YM_OK;
+}
+
+ym_status ym_autotune(ym_ctx *c, const ym_lexicon *L, const ym_batch *b, const ym_params *prm, int32_t reps,
+                      ym_tuning *best, double *best_ms) {
+  if (!c || !L || !best) return fail(YM_EINVAL, "NULL argument");
+  if (reps < 1 || reps > 1000) return fail(YM_EINVAL, "reps must be in 1..1000");
+  ym_status s;
+  if ((s = check_params(prm))) return s;
+  HostBatchInfo info;
+  if ((s = check_host_batch(b, info))) return s;
+  const int64_t P = b->n_pairs;
+  hipSetDevice(c->device);
+  std::lock_guard<std::mutex> lk(c->mu);
+  DevBatch d;
+  if ((s = upload_batch(c, b, info, d))) return s;
+  ym_device_out o;
+  if ((s = alloc_outputs(c, P, capacity_of(b->src_doc_off, b->tgt_doc_off, P), o))) return s;
+  if ((s = ensure_table(c, prm, c->stream))) return s;
+  std::vector<std::pair<int64_t, int64_t>> chunks;
+  const size_t head = trans_bytes(info.n_src_tok);
+  const size_t full = full_workspace(b->src_doc_off, b->tgt_doc_off, P, info.n_src_tok);
+  const size_t wsb = std::max(std::min(full, c->arena_limit + head), min_workspace(b->src_doc_off, b->tgt_doc_off, P, info.n_src_tok));
+  if ((s = plan_chunks(b->src_doc_off, b->tgt_doc_off, P, wsb - head, chunks))) return s;
+  // the workspace is sized for the smallest items (the most of them), before the head is written
+  size_t need = 256;
+  for (auto &ck : chunks) {
+    Chunk ch;
+    ch.layout(b->src_doc_off, b->tgt_doc_off, ck.first, ck.second, kMinItemRows);
+    need = std::max(need, ch.bytes);
+  }
+  if ((s = c->ws.reserve(head + need))) return s;
+  if ((s = translate_batch(c, L, d, (char *)c->ws.ptr, c->stream))) return s;
+  char *ws = (char *)c->ws.ptr + head;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (!e) e = hipEventCreate(&e1);
+  if (e) {
+    if (e0) hipEventDestroy(e0);
+    return hip_fail(e, "event create");
+  }
+  const ym_tuning before{c->sim_variant, c->item_rows, c->nw_pairs_per_group};
+  auto time_cfg = [&](const ym_tuning &t, double &ms) -> ym_status {
+    apply_tuning(c, t);
+    std::vector<Chunk> lay(chunks.size());
+    for (size_t k = 0; k < chunks.size(); k++)
+      lay[k].layout(b->src_doc_off, b->tgt_doc_off, chunks[k].first, chunks[k].second, t.item_rows);
+    ym_status st;
+    for (int r = -1; r < reps; r++) {  // one untimed pass first
+      if (r == 0 && (e = hipEventRecord(e0, c->stream))) return hip_fail(e, "event record");
+      for (auto &ch : lay)
+        if ((st = run_chunk(c, L, d, prm, b->src_doc_off, b->tgt_doc_off, ch, ws, o, c->stream, nullptr))) return st;
+    }
+    float f = 0.0f;
+    if ((e = hipEventRecord(e1, c->stream)) || (e = hipEventSynchronize(e1)) || (e = hipEventElapsedTime(&f, e0, e1)))
+      return hip_fail(e, "event timing");
+    ms = (double)f / reps;
+    return YM_OK;
+  };
+  ym_tuning win = before;
+  double win_ms = 1e300;
+  // similarity kernel and item size first (the NW launch is the same for all of them) ...
+  for (int v = 1; v >= 0 && !s; v--)
+    for (int rows : {64, 128, 256}) {
+      const ym_tuning t{v, rows, before.nw_pairs_per_group};
+      double ms = 0;
+      if ((s = time_cfg(t, ms))) break;
+      if (ms < win_ms) {
+        win_ms = ms;
+        win = t;
+      }
+    }
+  // ... then the NW workgroup size with that choice
+  for (int ppg : {1, 2, 4}) {
+    if (s) break;
+    if (ppg == win.nw_pairs_per_group) continue;
+    const ym_tuning t{win.sim_kernel, win.item_rows, ppg};
+    double ms = 0;
+    if ((s = time_cfg(t, ms))) break;
+    if (ms < win_ms) {
+      win_ms = ms;
+      win = t;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (s) {
+    apply_tuning(c, before);
+    return s;
+  }
+  apply_tuning(c, win);
+  *best = win;
+  if (best_ms) *best_ms = win_ms;
+  return YM_OK;
 }
 
 ym_status ym_nw_align(ym_ctx *c, const float *S, const int32_t *n, const int32_t *m, int64_t n_pairs, float gap,
@@ -554,7 +682,7 @@ ym_status ym_nw_align(ym_ctx *c, const float *S, const int32_t *n, const int32_t
   std::vector<Chunk> lay(chunks.size());
   size_t need = 256;
   for (size_t k = 0; k < chunks.size(); k++) {
-    lay[k].layout(sdo.data(), tdo.data(), chunks[k].first, chunks[k].second);
+    lay[k].layout(sdo.data(), tdo.data(), chunks[k].first, chunks[k].second, c->item_rows);
     need = std::max(need, lay[k].bytes);
   }
   if ((s = c->ws.reserve(need))) {

@@ -278,7 +278,7 @@ __device__ __forceinline__ int64_t readlane64(int64_t v, int k) {
   return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
-static_assert(kItemRows / kSimWaves <= 64, "one lane per row of a wave");
+static_assert(kMaxItemRows / kSimWaves <= 64, "one lane per row of a wave");
 
 __global__ __launch_bounds__(kSimThreads, 3) void sim_kernel(SimArgs a) {
   __shared__ int2 uent[kUcap];
@@ -483,9 +483,9 @@ __global__ __launch_bounds__(kSimThreads, 3) void sim_kernel(SimArgs a) {
       // per target token serves both rows.  The translations of the next two
       // rows are fetched while these are worked on.
       auto fetch2 = [&](int k) -> int4 {
-        const int64_t b0 = readlane64(rsb, min(k, 31)), b1 = readlane64(rsb, min(k + 1, 31));
-        const int n0 = k < nrows ? __builtin_amdgcn_readlane(rlen, min(k, 31)) : 0;
-        const int n1 = k + 1 < nrows ? __builtin_amdgcn_readlane(rlen, min(k + 1, 31)) : 0;
+        const int64_t b0 = readlane64(rsb, min(k, 63)), b1 = readlane64(rsb, min(k + 1, 63));
+        const int n0 = k < nrows ? __builtin_amdgcn_readlane(rlen, min(k, 63)) : 0;
+        const int n1 = k + 1 < nrows ? __builtin_amdgcn_readlane(rlen, min(k + 1, 63)) : 0;
         const int q = lane & 31, len = lane < 32 ? n0 : n1;
         const bool ok = q < len && len <= kPosBits;
         return ok ? a.trans[(lane < 32 ? b0 : b1) + q] : make_int4(-1, -1, -1, -1);
@@ -854,8 +854,6 @@ __global__ __launch_bounds__(kTileThreads) void sim_tile_kernel(SimArgs a) {
     if (m <= 0 || it.i1 <= it.i0) continue;
     const int64_t *toffs = a.tgt_sent_off + d.tgt_sent0;
     const int64_t *soffs = a.src_sent_off + d.src_sent0;
-    const int r0 = it.i0 + 64 * wv;
-    const int R = max(0, min(64, it.i1 - r0));
 
     for (int j0 = 0; j0 < m;) {
       if (tid == 0) {
@@ -927,7 +925,8 @@ __global__ __launch_bounds__(kTileThreads) void sim_tile_kernel(SimArgs a) {
       }
       __syncthreads();
 
-      if (R > 0) {
+      for (int r0 = it.i0 + 64 * wv; r0 < it.i1; r0 += 64 * kTileWaves) {  // 64-row groups of the item
+        const int R = min(64, it.i1 - r0);
         TileCtx tc;
         tc.ukey = ukey;
         tc.ulid = ulid;
@@ -1082,7 +1081,7 @@ __device__ __forceinline__ void nw_steps(const float (&buf)[kNwUnroll], float rb
 template <bool kLds>
 __device__ __forceinline__ void nw_pair(const NwArgs &a, const PairDesc &d, int64_t p, uint32_t *dirs,
                                         float *rowbuf) {
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63;
   const int n = d.n, m = d.m;
   const float g = a.gap;
   const int Wr = nw_dir_row_words(m);
@@ -1279,11 +1278,16 @@ __device__ __forceinline__ void nw_pair(const NwArgs &a, const PairDesc &d, int6
   }
 }
 
-__global__ __launch_bounds__(64) void nw_kernel(NwArgs a) {
-  __shared__ uint32_t sdir[kDirLds];
-  __shared__ float srow[kRowLds];
-  const int64_t p = blockIdx.x;
+// NPW pairs per workgroup, one wave each (waves never synchronise with each other).
+template <int NPW>
+__global__ __launch_bounds__(64 * NPW) void nw_kernel(NwArgs a) {
+  __shared__ uint32_t sdir_all[NPW][kDirLds];
+  __shared__ float srow_all[NPW][kRowLds];
+  const int wv = NPW == 1 ? 0 : __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t p = (int64_t)blockIdx.x * NPW + wv;
   if (p >= a.n_pairs) return;
+  uint32_t *sdir = sdir_all[wv];
+  float *srow = srow_all[wv];
   const PairDesc d = a.descs[p];
   if (d.dir_off < 0 && d.row_off < 0)
     nw_pair<true>(a, d, p, sdir, srow);
@@ -1464,9 +1468,21 @@ hipError_t launch_similarity(const SimArgs &a, int grid, int variant, hipStream_
   return hipGetLastError();
 }
 
-hipError_t launch_nw(const NwArgs &a, hipStream_t st) {
+hipError_t launch_nw(const NwArgs &a, int pairs_per_group, hipStream_t st) {
   if (a.n_pairs <= 0) return hipSuccess;
-  hipLaunchKernelGGL(nw_kernel, dim3((unsigned)a.n_pairs), dim3(64), 0, st, a);
+  switch (pairs_per_group) {
+    case 1:
+      hipLaunchKernelGGL(nw_kernel<1>, dim3((unsigned)a.n_pairs), dim3(64), 0, st, a);
+      break;
+    case 2:
+      hipLaunchKernelGGL(nw_kernel<2>, dim3((unsigned)((a.n_pairs + 1) / 2)), dim3(128), 0, st, a);
+      break;
+    case 4:
+      hipLaunchKernelGGL(nw_kernel<4>, dim3((unsigned)((a.n_pairs + 3) / 4)), dim3(256), 0, st, a);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

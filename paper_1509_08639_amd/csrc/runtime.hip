@@ -106,7 +106,7 @@ static inline bool nw_needs_global_row(int64_t n, int64_t m) { return n > 64 && 
 
 size_t pair_bytes(int64_t n, int64_t m) {
   size_t b = sizeof(PairDesc) + 4 /*count*/ + 8 /*moves off*/;
-  b += (size_t)((n + kItemRows - 1) / kItemRows) * sizeof(SimItem);
+  b += (size_t)((n + kMinItemRows - 1) / kMinItemRows) * sizeof(SimItem);  // bound over item sizes
   b += (size_t)score_slots(n, m) * 4;
   if (nw_needs_global_dirs(n, m)) b += (size_t)(n * nw_dir_row_words(m)) * 4;
   if (nw_needs_global_row(n, m)) b += (size_t)(m + 1) * 4;
@@ -116,7 +116,8 @@ size_t pair_bytes(int64_t n, int64_t m) {
 
 static const size_t kChunkSlack = 16 * 256;  // alignment padding of the regions
 
-ym_status Chunk::layout(const int64_t *sdo, const int64_t *tdo, int64_t p0_, int64_t p1_) {
+ym_status Chunk::layout(const int64_t *sdo, const int64_t *tdo, int64_t p0_, int64_t p1_, int item_rows_) {
+  item_rows = item_rows_;
   p0 = p0_;
   p1 = p1_;
   np = p1 - p0;
@@ -128,7 +129,7 @@ ym_status Chunk::layout(const int64_t *sdo, const int64_t *tdo, int64_t p0_, int
   slots = 0;
   for (int64_t p = p0; p < p1; p++) {
     const int64_t n = sdo[p + 1] - sdo[p], m = tdo[p + 1] - tdo[p];
-    if (n > 0 && m > 0) n_items += (n + kItemRows - 1) / kItemRows;
+    if (n > 0 && m > 0) n_items += (n + item_rows - 1) / item_rows;
     cells += n * m;
     s_slots += score_slots(n, m);
     if (nw_needs_global_dirs(n, m)) dir_words += n * nw_dir_row_words(m);
@@ -192,11 +193,11 @@ void Chunk::fill_host(const int64_t *sdo, const int64_t *tdo, char *host) const 
       d.row_off = -1;
     }
     if (n > 0 && m > 0)
-      for (int64_t i0 = 0; i0 < n; i0 += kItemRows) {
+      for (int64_t i0 = 0; i0 < n; i0 += item_rows) {
         SimItem &x = items[it++];
         x.pair = (int32_t)(p - p0);
         x.i0 = (int32_t)i0;
-        x.i1 = (int32_t)std::min<int64_t>(n, i0 + kItemRows);
+        x.i1 = (int32_t)std::min<int64_t>(n, i0 + item_rows);
         x.pad = 0;
       }
     moff[p - p0] = mv;
@@ -588,7 +589,7 @@ ym_status run_chunk(ym_ctx *c, const ym_lexicon *L, const DevBatch &b, const ym_
   if (n.moves) n.moves += dbg->moves_base;
   {
     KernelTimer kt(c, 1, st);
-    e = launch_nw(n, st);
+    e = launch_nw(n, c->nw_pairs_per_group, st);
   }
   if (e != hipSuccess) return hip_fail(e, "nw kernel");
   {

@@ -116,7 +116,7 @@ ym_status launch_step(ym_server *S, Slot &sl) {
                s4 = a256((size_t)ntt * 4 + 4);
   const size_t in_bytes = s1 + s2 + s3 + s4;
   Chunk ch;
-  ch.layout(sl.sdo.data(), sl.tdo.data(), 0, P);
+  ch.layout(sl.sdo.data(), sl.tdo.data(), 0, P, S->ctx->item_rows);
   sl.cap = ch.slots;
   const size_t o1 = a256((size_t)(P + 1) * 8), o2 = a256((size_t)P * 4 + 4), o3 = a256((size_t)sl.cap * 4 + 4);
   const size_t out_bytes = o1 + o2 + 3 * o3;

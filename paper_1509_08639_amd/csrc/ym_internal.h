@@ -20,6 +20,7 @@ constexpr int kJcap = 64;               // max target sentences per chunk (one p
 constexpr int kTdocCap = kTcap + 3 * kJcap;  // staged ids, each sentence padded to a multiple of 4
 static_assert(kJcap <= kSimThreads && kJcap == 64, "one lane per target sentence of a chunk");
 constexpr int kItemRows = 128;          // source sentences per work item (two 64-row strips)
+constexpr int kMinItemRows = 64, kMaxItemRows = 256;  // range of the tunable rows per similarity item
 constexpr int kMaxSentTokens = 1024;    // longest sentence the host entry points accept
 constexpr int64_t kMaxDocSents = 1 << 22;  // most sentences per document (one score strip stays below 2 GiB)
 constexpr int kTabLen = 64;             // score table covers sentence lengths < 64
@@ -116,7 +117,7 @@ hipError_t launch_translate(const int32_t *tok, int64_t n, const LexDev &L, int4
 hipError_t launch_score_table(float w0, float w1, float w2, float w3, float *table, hipStream_t st);
 // variant 0: bit-sliced tile kernel; 1: lane-per-target-sentence kernel
 hipError_t launch_similarity(const SimArgs &a, int grid, int variant, hipStream_t st);
-hipError_t launch_nw(const NwArgs &a, hipStream_t st);
+hipError_t launch_nw(const NwArgs &a, int pairs_per_group, hipStream_t st);
 hipError_t launch_scan(const int32_t *counts, int64_t n, int64_t *pair_off_at_p0, int first, hipStream_t st);
 hipError_t launch_compact(const PairDesc *descs, int64_t n_pairs, const int32_t *counts, const int64_t *pair_off_at_p0,
                           const int32_t *slot_src, const int32_t *slot_tgt, const float *slot_score, int32_t *out_src,

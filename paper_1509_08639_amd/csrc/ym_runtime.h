@@ -54,7 +54,8 @@ struct Chunk {
   int64_t p0 = 0, p1 = 0, np = 0, n_items = 0, cells = 0, s_slots = 0, dir_words = 0, row_floats = 0, slots = 0;
   size_t off_descs = 0, off_items = 0, off_S = 0, off_dirs = 0, off_rows = 0, off_ssrc = 0, off_stgt = 0,
          off_sscore = 0, off_counts = 0, off_moves_off = 0, bytes = 0, host_bytes = 0;
-  ym_status layout(const int64_t *sdo, const int64_t *tdo, int64_t p0, int64_t p1);
+  int item_rows = kItemRows;  // source sentences per similarity work item
+  ym_status layout(const int64_t *sdo, const int64_t *tdo, int64_t p0, int64_t p1, int item_rows);
   void fill_host(const int64_t *sdo, const int64_t *tdo, char *host) const;
 };
 
@@ -93,7 +94,10 @@ struct ym_ctx {
   ym::HostBuf host_out;
   float table_w[4] = {0, 0, 0, 0};
   bool table_valid = false;
+  // launch configuration (ym_set_tuning / ym_autotune; read when work is enqueued)
   int sim_variant = 1;  // similarity kernel: 1 lane per target sentence (default), 0 bit-sliced tiles (YM_SIM_KERNEL=tile)
+  int item_rows = ym::kItemRows;  // source sentences per similarity work item
+  int nw_pairs_per_group = 1;     // NW workgroup size in pairs (one wave each)
   // kernel timing
   bool prof = false;
   std::mutex prof_mu;

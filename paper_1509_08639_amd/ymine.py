@@ -29,7 +29,8 @@ EXPORTS = [
     "ym_create", "ym_destroy", "ym_last_error", "ym_version", "ym_lexicon_load", "ym_lexicon_free",
     "ym_lexicon_stats", "ym_mine", "ym_result_free", "ym_mine_per_pair", "ym_mine_device_capacity",
     "ym_mine_device_workspace", "ym_mine_device_workspace_min", "ym_mine_device", "ym_similarity",
-    "ym_nw_align", "ym_tune", "ym_mine_bidirectional", "ym_profile_enable", "ym_profile_read", "ym_server_start", "ym_submit", "ym_poll", "ym_server_next_done", "ym_cancel",
+    "ym_nw_align", "ym_tune", "ym_mine_bidirectional", "ym_set_tuning", "ym_get_tuning", "ym_autotune",
+    "ym_profile_enable", "ym_profile_read", "ym_server_start", "ym_submit", "ym_poll", "ym_server_next_done", "ym_cancel",
     "ym_server_stop",
     "ym_server_stats",
 ]
@@ -67,6 +68,13 @@ class DeviceBatch(C.Structure):
 
 class DeviceOut(C.Structure):
     _fields_ = [("pair_off", vp), ("src_idx", vp), ("tgt_idx", vp), ("score", vp), ("align_score", vp)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("sim_kernel", C.c_int32), ("item_rows", C.c_int32), ("nw_pairs_per_group", C.c_int32)]
+
+    def as_dict(self):
+        return dict(sim_kernel=self.sim_kernel, item_rows=self.item_rows, nw_pairs_per_group=self.nw_pairs_per_group)
 
 
 class ServerOpts(C.Structure):
@@ -109,6 +117,9 @@ def lib():
                               P(P(Result))]
     L.ym_tune.argtypes = [vp, vp, P(Batch), P(f32), P(f32), i32, P(f32), i32, P(i64), P(i32), P(i32), P(i64), P(i64)]
     L.ym_mine_bidirectional.argtypes = [vp, vp, vp, P(Batch), P(Params), P(Params), P(P(Result))]
+    L.ym_set_tuning.argtypes = [vp, P(Tuning)]
+    L.ym_get_tuning.argtypes = [vp, P(Tuning)]
+    L.ym_autotune.argtypes = [vp, vp, P(Batch), P(Params), i32, P(Tuning), P(C.c_double)]
     L.ym_profile_enable.argtypes = [vp, C.c_int]
     L.ym_profile_read.argtypes = [vp, P(C.c_double), P(i64)]
     L.ym_server_start.argtypes = [vp, vp, P(Params), P(ServerOpts), P(vp)]
@@ -325,6 +336,29 @@ def mine_bidirectional(ctx: Context, lex_fwd: Lexicon, lex_rev: Lexicon, corpus,
     _check(lib().ym_mine_bidirectional(ctx.h, lex_fwd.h, lex_rev.h, C.byref(hb.b), C.byref(pf), C.byref(pr),
                                        C.byref(rp)))
     return _result_to_numpy(rp)
+
+
+def set_tuning(ctx: Context, sim_kernel: int, item_rows: int, nw_pairs_per_group: int):
+    """ym_set_tuning."""
+    t = Tuning(sim_kernel, item_rows, nw_pairs_per_group)
+    _check(lib().ym_set_tuning(ctx.h, C.byref(t)))
+
+
+def get_tuning(ctx: Context) -> dict:
+    """ym_get_tuning."""
+    t = Tuning()
+    _check(lib().ym_get_tuning(ctx.h, C.byref(t)))
+    return t.as_dict()
+
+
+def autotune(ctx: Context, lex: Lexicon, corpus, w, gap, threshold, reps: int = 3):
+    """ym_autotune on a sample batch: (chosen configuration, its ms per pass)."""
+    hb = _HostBatch(corpus)
+    p = params(w, gap, threshold)
+    t = Tuning()
+    ms = C.c_double()
+    _check(lib().ym_autotune(ctx.h, lex.h, C.byref(hb.b), C.byref(p), int(reps), C.byref(t), C.byref(ms)))
+    return t.as_dict(), ms.value
 
 
 class DeviceMiner:

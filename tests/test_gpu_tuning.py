@@ -1,0 +1,78 @@
+"""Launch configurations and the autotuner: every configuration gives the same
+results (they only change how work is split over workgroups), and the
+autotuner applies a valid one."""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+from . import parity
+
+pytestmark = pytest.mark.gpu
+
+F32 = np.float32
+CONFIGS = list(itertools.product([1, 0], [64, 128, 256], [1, 2, 4]))
+
+
+@pytest.fixture(scope="module")
+def ym():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1509_08639_amd import ymine
+    return ymine
+
+
+def _same(a, b):
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_every_configuration_gives_the_same_result(ym):
+    ctx = ym.Context(0)
+    lex = parity.random_lexicon(21)
+    # more than 256 source sentences in some pairs: several items per pair for every item size
+    c = parity.random_corpus(21, n_pairs=24, nmax=300, mmax=150, lmax_src=40, lmax_tgt=35)
+    w = np.array([-1.5, 3.0, 2.0, 0.5], np.float32)
+    L = ctx.lexicon(lex.src_ids, lex.off, lex.tgt_ids)
+    assert ym.get_tuning(ctx) == dict(sim_kernel=1, item_rows=128, nw_pairs_per_group=1)
+    ref = ym.mine(ctx, L, c, w, -0.2, 0.5)
+    S_ref, ms_ref, mt_ref = ym.similarity(ctx, L, c, w)
+    OL = oracle.default().lexicon(lex.src_ids, lex.off, lex.tgt_ids)
+    want = oracle.default().mine(OL, c, w, F32(-0.2), F32(0.5))
+    parity.compare_mined(oracle.default(), OL, c, w, F32(-0.2), F32(0.5), ref, want, S_ref)
+    for sk, rows, ppg in CONFIGS:
+        ym.set_tuning(ctx, sk, rows, ppg)
+        assert ym.get_tuning(ctx) == dict(sim_kernel=sk, item_rows=rows, nw_pairs_per_group=ppg)
+        _same(ref, ym.mine(ctx, L, c, w, -0.2, 0.5))
+        S, ms, mt = ym.similarity(ctx, L, c, w)
+        assert np.array_equal(S, S_ref) and np.array_equal(ms, ms_ref) and np.array_equal(mt, mt_ref), (sk, rows)
+
+
+def test_set_tuning_rejects_other_values(ym):
+    ctx = ym.Context(0)
+    for bad in [(2, 128, 1), (1, 96, 1), (1, 512, 1), (1, 128, 3), (0, 128, 8)]:
+        with pytest.raises(ym.YmError):
+            ym.set_tuning(ctx, *bad)
+    assert ym.get_tuning(ctx) == dict(sim_kernel=1, item_rows=128, nw_pairs_per_group=1)
+
+
+def test_autotune_applies_a_valid_configuration(ym):
+    ctx = ym.Context(0)
+    cfg = synth.CONFIGS[1]
+    lex = synth.make_lexicon(cfg)
+    c = synth.generate(cfg, lex, pair_ids=np.arange(0, 10000, 25))
+    w = synth.weights(cfg.seed)
+    L = ctx.lexicon(lex.src_ids, lex.off, lex.tgt_ids)
+    ref = ym.mine(ctx, L, c, w, -0.2, 0.5)
+    best, ms = ym.autotune(ctx, L, c, w, -0.2, 0.5, reps=2)
+    assert (best["sim_kernel"], best["item_rows"], best["nw_pairs_per_group"]) in CONFIGS
+    assert ms > 0
+    assert ym.get_tuning(ctx) == best
+    _same(ref, ym.mine(ctx, L, c, w, -0.2, 0.5))
+    with pytest.raises(ym.YmError):
+        ym.autotune(ctx, L, c, w, -0.2, 0.5, reps=0)
+    assert ym.get_tuning(ctx) == best
