@@ -194,6 +194,8 @@ def main():
     ap.add_argument("--per-pair-sample", type=int, default=1000, help="pairs timed in the plain per-pair form")
     ap.add_argument("--serve-seconds", type=float, default=5.0, help="length of the served arrival trace (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=2000.0, help="Poisson arrival rate of the served trace")
+    ap.add_argument("--autotune-pairs", type=int, default=10000,
+                    help="sample size for the autotuner before the timed region (0: default configuration)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates the HBM byte counters) and exit")
     args = ap.parse_args()
@@ -232,6 +234,14 @@ def main():
 
     ctx = ymine.Context(0)
     L = ctx.lexicon(lex.src_ids, lex.off, lex.tgt_ids)
+    # autotuner (untimed): launch configuration picked on a sample of the batch
+    tuning = None
+    if args.autotune_pairs > 0:
+        sample = corpus.subset(np.linspace(0, corpus.n_pairs - 1, min(args.autotune_pairs, corpus.n_pairs)).astype(int))
+        t = time.time()
+        best, best_ms = ymine.autotune(ctx, L, sample, w, gap, tau, reps=5)
+        tuning = dict(best, sample_pairs=sample.n_pairs, sample_ms=best_ms, seconds=round(time.time() - t, 2))
+        log(f"[bench] autotune: {tuning}")
     dm = ymine.DeviceMiner(ctx, L, corpus)
     torch.cuda.synchronize()
 
@@ -345,7 +355,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": cfg.name, "n_pairs": corpus.n_pairs, "cells": cells,
                    "src_tokens": st["src_tokens"], "tgt_tokens": st["tgt_tokens"], "gap": float(gap),
-                   "threshold": float(tau), "parallelism": "single GPU"},
+                   "threshold": float(tau), "parallelism": "single GPU", "tuning": tuning},
         "gcups": gcups,
         "mined_pairs": n_mined,
         "kernels": kern,
