@@ -100,59 +100,69 @@ def served(ctx_cls, ymine, synth, seconds, rate, log_every=2.0):
     prm = ymine.params(w, -0.2, 0.5)
     out = {}
 
-    # (a) server
-    srv = ymine.Server(ctx, L, w, -0.2, 0.5, max_pairs_per_step=512, max_cells_per_step=1 << 25)
+    # (a) server, steps launched eagerly and captured into hipGraphs
     ymine.mine_prepared(ctx, L, reqs[0], prm)  # warm the kernels
-    done_ns = np.zeros(n_req, np.int64)
-    ticket_of = {}
-    lock = threading.Lock()
-    t0 = time.monotonic_ns() + 200_000_000
-
-    def submitter():
-        for k in range(n_req):
-            due = t0 + int(arr[k] * 1e9)
-            while True:
-                now = time.monotonic_ns()
-                if now >= due:
-                    break
-                time.sleep(min((due - now) / 1e9, 0.0005))
-            t = srv.submit_prepared(reqs[k])
-            with lock:
-                ticket_of[t] = k
-
-    th = threading.Thread(target=submitter)
-    th.start()
-    got = 0
     results_srv = {}
-    last = time.time()
-    while got < n_req:
-        r = srv.next_done(1_000_000)
-        if r is None:
-            continue
-        t, dn = r
-        with lock:
-            k = ticket_of.get(t)
-        while k is None:
-            time.sleep(0.0001)
+
+    def run_server(use_graph):
+        srv = ymine.Server(ctx, L, w, -0.2, 0.5, max_pairs_per_step=512, max_cells_per_step=1 << 25,
+                           use_graph=use_graph)
+        done_ns = np.zeros(n_req, np.int64)
+        ticket_of = {}
+        lock = threading.Lock()
+        t0 = time.monotonic_ns() + 200_000_000
+
+        def submitter():
+            for k in range(n_req):
+                due = t0 + int(arr[k] * 1e9)
+                while True:
+                    now = time.monotonic_ns()
+                    if now >= due:
+                        break
+                    time.sleep(min((due - now) / 1e9, 0.0005))
+                t = srv.submit_prepared(reqs[k])
+                with lock:
+                    ticket_of[t] = k
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        got = 0
+        last = time.time()
+        while got < n_req:
+            r = srv.next_done(1_000_000)
+            if r is None:
+                continue
+            t, dn = r
             with lock:
                 k = ticket_of.get(t)
-        res = srv.poll(t, 0)
-        done_ns[k] = dn
-        if k % 97 == 0:
-            results_srv[k] = res
-        got += 1
-        if time.time() - last > log_every:
-            log(f"[serve] server: {got}/{n_req} done")
-            last = time.time()
-    th.join()
-    stats = srv.stats()
-    srv.stop()
-    lat = (done_ns - (t0 + (arr * 1e9).astype(np.int64))) / 1e6
-    span = (done_ns.max() - t0) / 1e9
-    out["server"] = dict(p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
-                         mean_ms=float(lat.mean()), max_ms=float(lat.max()), throughput_pairs_per_s=n_req / span,
-                         steps=stats["steps"], pairs_per_step=stats["completed"] / max(stats["steps"], 1))
-    log(f"[serve] server {out['server']}")
+            while k is None:
+                time.sleep(0.0001)
+                with lock:
+                    k = ticket_of.get(t)
+            res = srv.poll(t, 0)
+            done_ns[k] = dn
+            if k % 97 == 0:
+                results_srv.setdefault(k, []).append(res)
+            got += 1
+            if time.time() - last > log_every:
+                log(f"[serve] server (graph={use_graph}): {got}/{n_req} done")
+                last = time.time()
+        th.join()
+        stats = srv.stats()
+        gstats = srv.graph_stats()
+        srv.stop()
+        lat = (done_ns - (t0 + (arr * 1e9).astype(np.int64))) / 1e6
+        span = (done_ns.max() - t0) / 1e9
+        r = dict(p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
+                 mean_ms=float(lat.mean()), max_ms=float(lat.max()), throughput_pairs_per_s=n_req / span,
+                 steps=stats["steps"], pairs_per_step=stats["completed"] / max(stats["steps"], 1))
+        if use_graph:
+            r.update(graph_instantiations=gstats["instantiations"], graph_updates=gstats["updates"])
+        log(f"[serve] server (graph={use_graph}) {r}")
+        return r
+
+    out["server"] = run_server(0)
+    out["server_graph"] = run_server(1)
 
     # (b) plain per-pair GPU form, FIFO on the same trace (bounded to the same wall time + 20 s)
     lat_pp = []
@@ -167,8 +177,8 @@ def served(ctx_cls, ymine, synth, seconds, rate, log_every=2.0):
         res = ymine.mine_prepared(ctx, L, reqs[k], prm, per_pair=True)
         fin = time.monotonic_ns()
         lat_pp.append((fin - due) / 1e6)
-        if k in results_srv:
-            same &= all(np.array_equal(res[x], results_srv[k][x]) for x in res)
+        for other in results_srv.get(k, []):
+            same &= all(np.array_equal(res[x], other[x]) for x in res)
         if fin > deadline:
             break
     lat_pp = np.array(lat_pp)

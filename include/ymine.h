@@ -279,7 +279,7 @@ ym_status ym_profile_read(ym_ctx *ctx, double ms[4], int64_t launches[4]);
 typedef struct {
   int32_t max_pairs_per_step; /* descriptor-table capacity of one batch step */
   int64_t max_cells_per_step; /* cap on sum n*m admitted into one step */
-  int32_t use_graph;          /* capture the step's kernels in a hipGraph */
+  int32_t use_graph;          /* capture each step (copy-in, kernels, copy-out) in a hipGraph, updated in place between steps */
 } ym_server_opts;
 
 /* Start a serving loop over a resident lexicon and fixed parameters.  A
@@ -306,6 +306,9 @@ ym_status ym_cancel(ym_server *srv, uint64_t ticket);
 ym_status ym_server_stop(ym_server *srv);
 /* Counters: steps run, requests completed, cells processed. */
 ym_status ym_server_stats(const ym_server *srv, int64_t *steps, int64_t *completed, int64_t *cells);
+/* Graph mode (use_graph): executable graphs instantiated and updated in place
+ * (hipGraphExecUpdate) so far, over both step slots. */
+ym_status ym_server_graph_stats(const ym_server *srv, int64_t *instantiations, int64_t *updates);
 
 #ifdef __cplusplus
 }

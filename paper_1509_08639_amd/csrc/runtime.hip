@@ -514,7 +514,7 @@ ym_status run_chunk(ym_ctx *c, const ym_lexicon *L, const DevBatch &b, const ym_
                     const DebugOut *dbg, Staging *stg) {
   // plan -> pinned staging -> workspace (wait for the previous upload to have left the staging buffer)
   if (!stg) stg = &c->stage;
-  hipError_t e = hipEventSynchronize(stg->done);
+  hipError_t e = stg->caller_syncs ? hipSuccess : hipEventSynchronize(stg->done);
   if (e != hipSuccess) return hip_fail(e, "staging wait");
   ym_status s = stg->buf.reserve(ch.host_bytes);
   if (s) return s;
@@ -522,11 +522,12 @@ ym_status run_chunk(ym_ctx *c, const ym_lexicon *L, const DevBatch &b, const ym_
   const size_t dsz = align256((size_t)ch.np * sizeof(PairDesc));
   const size_t isz = align256((size_t)std::max<int64_t>(ch.n_items, 1) * sizeof(SimItem));
   const char *hp = (const char *)stg->buf.ptr;
+  // When the work is captured into a graph the caller records stg->done after launching it.
   if ((e = hipMemcpyAsync(ws + ch.off_descs, hp, dsz, hipMemcpyHostToDevice, st)) != hipSuccess ||
       (e = hipMemcpyAsync(ws + ch.off_items, hp + dsz, isz, hipMemcpyHostToDevice, st)) != hipSuccess ||
       (e = hipMemcpyAsync(ws + ch.off_moves_off, hp + dsz + isz, align256((size_t)ch.np * 8), hipMemcpyHostToDevice, st)) !=
           hipSuccess ||
-      (e = hipEventRecord(stg->done, st)) != hipSuccess)
+      (!stg->caller_syncs && (e = hipEventRecord(stg->done, st)) != hipSuccess))
     return hip_fail(e, "plan upload");
 
   const PairDesc *descs = (const PairDesc *)(ws + ch.off_descs);

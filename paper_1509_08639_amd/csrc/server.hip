@@ -21,6 +21,7 @@
 #include <deque>
 #include <mutex>
 #include <new>
+#include <string>
 #include <thread>
 #include <unordered_map>
 #include <vector>
@@ -52,6 +53,7 @@ struct Request {
   int state = kPending;
   bool cancel = false;
   ym_status status = YM_OK;
+  std::string error;  // why the request's step failed
   ym_result *result = nullptr;
 };
 
@@ -74,6 +76,8 @@ struct Slot {
   int64_t cap = 0;  // output capacity of the step
   size_t off_out = 0;
   ym_status launch_status = YM_OK;
+  hipGraphExec_t exec = nullptr;  // the last step's executable graph (graph mode)
+  int64_t graph_updates = 0, graph_instantiations = 0;
 };
 
 }  // namespace
@@ -143,8 +147,29 @@ ym_status launch_step(ym_server *S, Slot &sl) {
     tb += (int64_t)r->ttok.size();
   }
   char *d = (char *)sl.dev.ptr;
-  hipError_t e = hipMemcpyAsync(d, h, in_bytes, hipMemcpyHostToDevice, sl.stream);
-  if (e) return hip_fail(e, "step upload");
+  // Graph mode: the step's copies and kernels are captured into a graph; the
+  // previous step's executable graph is updated in place when the topology
+  // matches (hipGraphExecUpdate), else a new one is instantiated.  The slot's
+  // events are recorded after the launch, outside the graph.
+  const bool graph = S->opts.use_graph != 0;
+  sl.stage.caller_syncs = graph;
+  hipError_t e;
+  if (graph) {
+    // the staging buffer is free once the slot's previous step has read it
+    if ((e = hipEventSynchronize(sl.stage.done))) return hip_fail(e, "staging wait");
+    if ((e = hipStreamBeginCapture(sl.stream, hipStreamCaptureModeRelaxed))) return hip_fail(e, "begin capture");
+  }
+  auto abort_capture = [&]() {
+    if (!graph) return;
+    hipGraph_t g = nullptr;
+    if (hipStreamEndCapture(sl.stream, &g) == hipSuccess && g) hipGraphDestroy(g);
+    (void)hipGetLastError();
+  };
+  e = hipMemcpyAsync(d, h, in_bytes, hipMemcpyHostToDevice, sl.stream);
+  if (e) {
+    abort_capture();
+    return hip_fail(e, "step upload");
+  }
   DevBatch b;
   b.src_sent_off = (const int64_t *)d;
   b.tgt_sent_off = (const int64_t *)(d + s1);
@@ -154,7 +179,10 @@ ym_status launch_step(ym_server *S, Slot &sl) {
   b.n_tgt_sent = NT;
   b.n_src_tok = nts;
   b.n_tgt_tok = ntt;
-  if ((s = translate_batch(S->ctx, S->lex, b, d + in_bytes, sl.stream))) return s;
+  if ((s = translate_batch(S->ctx, S->lex, b, d + in_bytes, sl.stream))) {
+    abort_capture();
+    return s;
+  }
   char *ws = d + in_bytes + head;
   char *ob = ws + a256(ch.bytes);
   sl.off_out = in_bytes + head + a256(ch.bytes);
@@ -165,11 +193,44 @@ ym_status launch_step(ym_server *S, Slot &sl) {
   o.tgt_idx = (int32_t *)(ob + o1 + o2 + o3);
   o.score = (float *)(ob + o1 + o2 + 2 * o3);
   if ((s = run_chunk(S->ctx, S->lex, b, &S->prm, sl.sdo.data(), sl.tdo.data(), ch, ws, o, sl.stream, nullptr,
-                     &sl.stage)))
+                     &sl.stage))) {
+    abort_capture();
     return s;
+  }
   e = hipMemcpyAsync(sl.hout.ptr, ob, out_bytes, hipMemcpyDeviceToHost, sl.stream);
-  if (!e) e = hipEventRecord(sl.done, sl.stream);
-  if (e) return hip_fail(e, "step download");
+  if (e) {
+    abort_capture();
+    return hip_fail(e, "step download");
+  }
+  if (graph) {
+    hipGraph_t g = nullptr;
+    if ((e = hipStreamEndCapture(sl.stream, &g)) || !g) return hip_fail(e ? e : hipErrorUnknown, "end capture");
+    bool updated = false;
+    if (sl.exec) {
+      hipGraphNode_t err_node = nullptr;
+      hipGraphExecUpdateResult res = hipGraphExecUpdateError;
+      if (hipGraphExecUpdate(sl.exec, g, &err_node, &res) == hipSuccess && res == hipGraphExecUpdateSuccess) {
+        updated = true;
+        sl.graph_updates++;
+      } else {
+        (void)hipGetLastError();
+        hipGraphExecDestroy(sl.exec);
+        sl.exec = nullptr;
+      }
+    }
+    if (!updated) {
+      if ((e = hipGraphInstantiate(&sl.exec, g, nullptr, nullptr, 0))) {
+        hipGraphDestroy(g);
+        sl.exec = nullptr;
+        return hip_fail(e, "graph instantiate");
+      }
+      sl.graph_instantiations++;
+    }
+    hipGraphDestroy(g);
+    if ((e = hipGraphLaunch(sl.exec, sl.stream))) return hip_fail(e, "graph launch");
+    if ((e = hipEventRecord(sl.stage.done, sl.stream))) return hip_fail(e, "staging event");
+  }
+  if ((e = hipEventRecord(sl.done, sl.stream))) return hip_fail(e, "step event");
   return YM_OK;
 }
 
@@ -285,9 +346,11 @@ void scheduler(ym_server *S) {
           free_slot->busy = true;
           lk.unlock();
           const ym_status st = launch_step(S, *free_slot);
+          const std::string why = st != YM_OK ? std::string(ym_last_error()) : std::string();
           lk.lock();
           if (st != YM_OK) {
             hipStreamSynchronize(free_slot->stream);
+            for (Request *r : free_slot->reqs) r->error = why;
             finish_step(S, *free_slot, st);
             S->cv_done.notify_all();
           }
@@ -444,13 +507,14 @@ ym_status ym_poll(ym_server *S, uint64_t ticket, int64_t timeout_us, ym_result *
   S->all.erase(it);
   const int st = r->state;
   const ym_status code = r->status;
+  const std::string why = r->error;
   if (st == kDone) {
     *out = r->result;
     r->result = nullptr;
   }
   free_request(r);
   if (st == kCancelled) return fail(YM_ECANCELLED, "request %llu was cancelled", (unsigned long long)ticket);
-  if (st == kFailed) return fail(code, "request %llu failed", (unsigned long long)ticket);
+  if (st == kFailed) return fail(code, "request %llu failed: %s", (unsigned long long)ticket, why.c_str());
   return YM_OK;
 }
 
@@ -496,6 +560,7 @@ ym_status ym_server_stop(ym_server *S) {
     sl.hin.release();
     sl.hout.release();
     sl.stage.buf.release();
+    if (sl.exec) hipGraphExecDestroy(sl.exec);
     hipEventDestroy(sl.done);
     hipEventDestroy(sl.stage.done);
     hipStreamDestroy(sl.stream);
@@ -512,6 +577,20 @@ ym_status ym_server_stats(const ym_server *S, int64_t *steps, int64_t *completed
   if (steps) *steps = S->n_steps;
   if (completed) *completed = S->n_completed;
   if (cells) *cells = S->n_cells;
+  return YM_OK;
+}
+
+ym_status ym_server_graph_stats(const ym_server *S, int64_t *instantiations, int64_t *updates) {
+  if (!S) return fail(YM_EINVAL, "NULL server");
+  ym_server *T = const_cast<ym_server *>(S);
+  std::lock_guard<std::mutex> lk(T->mu);
+  int64_t a = 0, u = 0;
+  for (const Slot &sl : S->slots) {
+    a += sl.graph_instantiations;
+    u += sl.graph_updates;
+  }
+  if (instantiations) *instantiations = a;
+  if (updates) *updates = u;
   return YM_OK;
 }
 

@@ -75,6 +75,7 @@ ym_status plan_chunks(const int64_t *sdo, const int64_t *tdo, int64_t n_pairs, s
 struct Staging {
   HostBuf buf;
   hipEvent_t done = nullptr;
+  bool caller_syncs = false;  // the caller waits for and records `done` (work captured into a graph)
 };
 
 ym_status run_chunk(ym_ctx *c, const ym_lexicon *L, const DevBatch &b, const ym_params *prm, const int64_t *sdo,
@@ -127,7 +128,8 @@ struct KernelTimer {
   hipStream_t st;
   hipEvent_t a = nullptr, b = nullptr;
   KernelTimer(ym_ctx *c_, int kind_, hipStream_t st_) : c(c_), kind(kind_), st(st_) {
-    if (c && c->prof) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (c && c->prof && hipStreamIsCapturing(st, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone) {
       std::lock_guard<std::mutex> lk(c->prof_mu);
       a = c->ev_get();
       b = c->ev_get();

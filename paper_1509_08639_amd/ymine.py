@@ -32,7 +32,7 @@ EXPORTS = [
     "ym_nw_align", "ym_tune", "ym_mine_bidirectional", "ym_set_tuning", "ym_get_tuning", "ym_autotune",
     "ym_profile_enable", "ym_profile_read", "ym_server_start", "ym_submit", "ym_poll", "ym_server_next_done", "ym_cancel",
     "ym_server_stop",
-    "ym_server_stats",
+    "ym_server_stats", "ym_server_graph_stats",
 ]
 
 
@@ -129,6 +129,7 @@ def lib():
     L.ym_cancel.argtypes = [vp, u64]
     L.ym_server_stop.argtypes = [vp]
     L.ym_server_stats.argtypes = [vp, P(i64), P(i64), P(i64)]
+    L.ym_server_graph_stats.argtypes = [vp, P(i64), P(i64)]
     _lib = L
     return L
 
@@ -452,6 +453,11 @@ class Server:
         a, b, c = i64(), i64(), i64()
         _check(lib().ym_server_stats(self.h, C.byref(a), C.byref(b), C.byref(c)))
         return dict(steps=a.value, completed=b.value, cells=c.value)
+
+    def graph_stats(self):
+        a, b = i64(), i64()
+        _check(lib().ym_server_graph_stats(self.h, C.byref(a), C.byref(b)))
+        return dict(instantiations=a.value, updates=b.value)
 
     def stop(self):
         if self.h:

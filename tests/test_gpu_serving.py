@@ -134,3 +134,33 @@ def test_malformed_and_cancelled(ym, setup):
         assert e.value.code == ym.YM_ENOTFOUND
     finally:
         srv.stop()
+
+
+def test_graph_mode_replays_match_eager(ym, setup):
+    """Steps captured in hipGraphs (updated in place between steps) give the
+    same results as the eager batch entry point, over several waves of
+    requests with eager work and synchronisation between the waves."""
+    cfg, lex, corpus, w, ctx, L = setup
+    batch = ym.mine(ctx, L, corpus, w, -0.2, 0.5)
+    srv = ym.Server(ctx, L, w, -0.2, 0.5, max_pairs_per_step=16, use_graph=1)
+    got = {}
+    try:
+        waves = [range(0, 40), range(40, 100), [7], [8], range(100, corpus.n_pairs)]
+        for wave in waves:
+            tickets = {srv.submit(corpus.subset([p])): p for p in wave}
+            for t, p in tickets.items():
+                got[p] = srv.poll(t)
+            # the program's own eager work between the replays
+            eager = ym.mine(ctx, L, corpus.subset(list(wave)[:5]), w, -0.2, 0.5)
+            assert eager["pair_off"][-1] >= 0
+        stats = srv.stats()
+        gs = srv.graph_stats()
+    finally:
+        srv.stop()
+    assert gs["instantiations"] >= 1
+    assert gs["instantiations"] + gs["updates"] == stats["steps"]
+    for p in range(corpus.n_pairs):
+        a, b = batch["pair_off"][p], batch["pair_off"][p + 1]
+        r = got[p]
+        assert np.array_equal(r["src_idx"], batch["src_idx"][a:b]) and np.array_equal(r["tgt_idx"], batch["tgt_idx"][a:b]), p
+        assert np.array_equal(r["score"], batch["score"][a:b]) and r["align_score"][0] == batch["align_score"][p], p
