@@ -17,6 +17,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "ym_internal.h"
 
 namespace ym {
@@ -998,6 +1000,47 @@ struct NwLane {
   uint32_t dw;
 };
 
+// Hand-off of strip bottom rows between the waves of one workgroup that
+// sweeps a large pair with several waves (strip s on wave s mod W): the slot
+// of wave w holds (strip << 32) | (columns of that strip's bottom row
+// published so far).  A default-constructed pipe (no slots) is the one-wave
+// sweep, where strips run in order and nothing is waited for.
+struct NwPipe {
+  int64_t *prog = nullptr;  // LDS slots, one per wave
+  int W = 1;
+  int *abort = nullptr;  // LDS flag: a wait ran past its time limit
+};
+
+// Wall-clock limit of one wait (ticks of the constant 100 MHz counter): far
+// above any legitimate wait, which is at most one strip sweep.
+constexpr uint64_t kNwWaitTicks = 2000000000ull;  // 20 s
+
+// Wait until strip `strip` has published at least `cols` columns (or has been
+// finished and its wave moved on).  Wave-uniform; false if the limit was hit.
+__device__ __forceinline__ bool nw_wait(const NwPipe &pp, int strip, int cols) {
+  int64_t *slot = pp.prog + (strip % pp.W);
+  const uint64_t t0 = wall_clock64();
+  for (;;) {
+    const int64_t v = __hip_atomic_load(slot, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+    const int vs = (int)(v >> 32), vc = (int)(uint32_t)v;
+    if (vs > strip || (vs == strip && vc >= cols)) return true;
+    if (__hip_atomic_load(pp.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) return false;
+    if (wall_clock64() - t0 > kNwWaitTicks) {
+      __hip_atomic_store(pp.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+}
+
+// Publish `cols` columns of strip `strip`'s bottom row (after this wave's row stores).
+__device__ __forceinline__ void nw_publish(const NwPipe &pp, int strip, int cols) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  if ((threadIdx.x & 63) == 0)
+    __hip_atomic_store(pp.prog + (strip % pp.W), ((int64_t)strip << 32) | (uint32_t)cols, __ATOMIC_RELEASE,
+                       __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 // Scores of the next 16 steps for this lane: step t reads slot
 // (t - 1) * R + lane of the strip (anti-diagonal t - 1).  The strip is read
 // through a buffer resource whose range is the strip, so reads before its
@@ -1006,8 +1049,10 @@ struct NwLane {
 // lane k also fetches the previous strip's bottom-row value H[64s][t] of the
 // block's step k (handed to lane 0 by readlane).
 __device__ __forceinline__ void nw_prefetch(float (&buf)[kNwUnroll], float &rbv, __amdgpu_buffer_rsrc_t rs,
-                                            const float *rowbuf, bool use_row, int &d, int lane, int R, int m) {
+                                            const float *rowbuf, bool use_row, int &d, int lane, int R, int m,
+                                            const NwPipe &pp, int s) {
   const int t = d + 1 + lane;
+  if (pp.prog && use_row) nw_wait(pp, s - 1, min(m, d + kNwUnroll) + 1);
   rbv = (use_row && lane < kNwUnroll && t <= m) ? rowbuf[t] : 0.0f;
 #pragma unroll
   for (int k = 0; k < kNwUnroll; k++) {
@@ -1027,7 +1072,7 @@ __device__ __forceinline__ void nw_prefetch(float (&buf)[kNwUnroll], float &rbv,
 template <bool kTail, bool kTop>
 __device__ __forceinline__ void nw_steps(const float (&buf)[kNwUnroll], float rbv, int t0, int tend, NwLane &L,
                                          int lane, int i, bool rowok, int lastlane, bool keep_row, int m, int Wr,
-                                         float g, uint32_t *dirs, float *rowbuf) {
+                                         float g, uint32_t *dirs, float *rowbuf, const NwPipe &pp, int s) {
   float hb[kNwUnroll];
   if (kTail) {
 #pragma unroll
@@ -1075,68 +1120,81 @@ __device__ __forceinline__ void nw_steps(const float (&buf)[kNwUnroll], float rb
     }
     const int j = t0 + lane - lastlane;
     if (lane < kNwUnroll && j >= 0 && j <= m && t0 + lane <= tl) rowbuf[j] = v;
+    if (pp.prog) {
+      const int cols = min(m, tl - lastlane) + 1;
+      if (cols > 0) nw_publish(pp, s, cols);
+    }
   }
 }
 
-template <bool kLds>
-__device__ __forceinline__ void nw_pair(const NwArgs &a, const PairDesc &d, int64_t p, uint32_t *dirs,
-                                        float *rowbuf) {
+// One 64-row strip of a pair's sweep.  rowin: the previous strip's bottom
+// row (strips after the first), rowout: this strip's bottom row (strips before
+// the last; may be the same array as rowin for a one-wave sweep, whose reads
+// run ahead of its writes).  Returns H of the strip's last row at column m.
+__device__ __forceinline__ float nw_strip(const NwArgs &a, const PairDesc &d, int s, uint32_t *dirs,
+                                          const float *rowin, float *rowout, const NwPipe &pp) {
   const int lane = threadIdx.x & 63;
   const int n = d.n, m = d.m;
   const float g = a.gap;
   const int Wr = nw_dir_row_words(m);
-  const float *S = a.S + d.s_off;
-  float hnm = 0.0f;
-
-  if (n > 0 && m > 0) {
-    const int nstrips = (n + 63) >> 6;
-    for (int s = 0; s < nstrips; s++) {
-      const int i = s * 64 + lane + 1;
-      const bool rowok = i <= n;
-      const int R = min(64, n - s * 64);
-      const int lastlane = R - 1;
-      const bool keep_row = s + 1 < nstrips;
-      const float *blk = S + (int64_t)s * (m + 63) * 64;
-      const __amdgpu_buffer_rsrc_t rs =
-          __builtin_amdgcn_make_buffer_rsrc((void *)blk, (short)0, (int)((m + R - 1) * R * 4), kBufferFlags);
-      NwLane L{0.0f, 0.0f, -g, 0u};
-      const int tend = m + lastlane;
-      float bufA[kNwUnroll], bufB[kNwUnroll], rbA, rbB;
-      int cd = -1;  // prefetch cursor: step t reads diagonal t-1
-      const bool use_row = s > 0;
-      nw_prefetch(bufA, rbA, rs, rowbuf, use_row, cd, lane, R, m);
-      int t0 = 0;
-      // full blocks of 2 x 16 steps
-      for (; t0 + 2 * kNwUnroll - 1 <= tend; t0 += 2 * kNwUnroll) {
-        nw_prefetch(bufB, rbB, rs, rowbuf, use_row, cd, lane, R, m);
-        if (s == 0)
-          nw_steps<false, true>(bufA, rbA, t0, tend, L, lane, i, rowok, lastlane, keep_row, m, Wr, g, dirs, rowbuf);
-        else
-          nw_steps<false, false>(bufA, rbA, t0, tend, L, lane, i, rowok, lastlane, keep_row, m, Wr, g, dirs, rowbuf);
-        nw_prefetch(bufA, rbA, rs, rowbuf, use_row, cd, lane, R, m);
-        if (s == 0)
-          nw_steps<false, true>(bufB, rbB, t0 + kNwUnroll, tend, L, lane, i, rowok, lastlane, keep_row, m, Wr, g,
-                                dirs, rowbuf);
-        else
-          nw_steps<false, false>(bufB, rbB, t0 + kNwUnroll, tend, L, lane, i, rowok, lastlane, keep_row, m, Wr, g,
-                                 dirs, rowbuf);
-      }
-      // the rest: at most two blocks, the last one partial
-      for (; t0 <= tend; t0 += kNwUnroll) {
-        if (s == 0)
-          nw_steps<true, true>(bufA, rbA, t0, tend, L, lane, i, rowok, lastlane, keep_row, m, Wr, g, dirs, rowbuf);
-        else
-          nw_steps<true, false>(bufA, rbA, t0, tend, L, lane, i, rowok, lastlane, keep_row, m, Wr, g, dirs, rowbuf);
-        if (t0 + kNwUnroll <= tend) nw_prefetch(bufA, rbA, rs, rowbuf, use_row, cd, lane, R, m);
-      }
-      if (s == nstrips - 1) hnm = __shfl(L.h, lastlane);
-      wave_sync_mem();
-    }
-  } else {
-    float h = 0.0f;
-    for (int k = 0; k < n + m; k++) h = __fadd_rn(h, g);
-    hnm = h;
+  const int nstrips = (n + 63) >> 6;
+  const int i = s * 64 + lane + 1;
+  const bool rowok = i <= n;
+  const int R = min(64, n - s * 64);
+  const int lastlane = R - 1;
+  const bool keep_row = s + 1 < nstrips;
+  const float *blk = a.S + d.s_off + (int64_t)s * (m + 63) * 64;
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc((void *)blk, (short)0, (int)((m + R - 1) * R * 4), kBufferFlags);
+  NwLane L{0.0f, 0.0f, -g, 0u};
+  const int tend = m + lastlane;
+  float bufA[kNwUnroll], bufB[kNwUnroll], rbA, rbB;
+  int cd = -1;  // prefetch cursor: step t reads diagonal t-1
+  const bool use_row = s > 0;
+  nw_prefetch(bufA, rbA, rs, rowin, use_row, cd, lane, R, m, pp, s);
+  int t0 = 0;
+  // full blocks of 2 x 16 steps
+  for (; t0 + 2 * kNwUnroll - 1 <= tend; t0 += 2 * kNwUnroll) {
+    nw_prefetch(bufB, rbB, rs, rowin, use_row, cd, lane, R, m, pp, s);
+    if (s == 0)
+      nw_steps<false, true>(bufA, rbA, t0, tend, L, lane, i, rowok, lastlane, keep_row, m, Wr, g, dirs, rowout, pp, s);
+    else
+      nw_steps<false, false>(bufA, rbA, t0, tend, L, lane, i, rowok, lastlane, keep_row, m, Wr, g, dirs, rowout, pp, s);
+    nw_prefetch(bufA, rbA, rs, rowin, use_row, cd, lane, R, m, pp, s);
+    if (s == 0)
+      nw_steps<false, true>(bufB, rbB, t0 + kNwUnroll, tend, L, lane, i, rowok, lastlane, keep_row, m, Wr, g, dirs,
+                            rowout, pp, s);
+    else
+      nw_steps<false, false>(bufB, rbB, t0 + kNwUnroll, tend, L, lane, i, rowok, lastlane, keep_row, m, Wr, g, dirs,
+                             rowout, pp, s);
   }
+  // the rest: at most two blocks, the last one partial
+  for (; t0 <= tend; t0 += kNwUnroll) {
+    if (s == 0)
+      nw_steps<true, true>(bufA, rbA, t0, tend, L, lane, i, rowok, lastlane, keep_row, m, Wr, g, dirs, rowout, pp, s);
+    else
+      nw_steps<true, false>(bufA, rbA, t0, tend, L, lane, i, rowok, lastlane, keep_row, m, Wr, g, dirs, rowout, pp, s);
+    if (t0 + kNwUnroll <= tend) nw_prefetch(bufA, rbA, rs, rowin, use_row, cd, lane, R, m, pp, s);
+  }
+  return __shfl(L.h, lastlane);
+}
+
+// H[n][m] of a pair with no sentence on one side: the boundary alone.
+__device__ __forceinline__ float nw_boundary_only(int n, int m, float g) {
+  float h = 0.0f;
+  for (int k = 0; k < n + m; k++) h = __fadd_rn(h, g);
+  return h;
+}
+
+// Traceback, threshold filter and outputs of one pair (one wave), once the
+// sweep has written all direction words.
+template <bool kLds>
+__device__ __forceinline__ void nw_finish(const NwArgs &a, const PairDesc &d, int64_t p, const uint32_t *dirs,
+                                          float hnm) {
+  const int lane = threadIdx.x & 63;
+  const int n = d.n, m = d.m;
+  const int Wr = nw_dir_row_words(m);
+  const float *S = a.S + d.s_off;
 
   // traceback
   const int cap = min(n, m);
@@ -1191,30 +1249,65 @@ __device__ __forceinline__ void nw_pair(const NwArgs &a, const PairDesc &d, int6
     K = __shfl(K, 0);
     T = __shfl(T, 0);
   } else {
-    // wave-uniform walk (scalar unit).  Inside one direction word a run of L
-    // moves is skipped at once: the next cell that is not an L move is the
+    // Wave-uniform walk (scalar unit) over a window of direction words held
+    // in registers: lane q holds the three words of row wr0 - q that end at
+    // the word of column wj0 (the position where the window was loaded), so
+    // the walk reads them with readlane and reloads only when it leaves the
+    // window (64 rows up or about 32 columns left).  Inside a word a run of
+    // L moves is skipped at once: the next cell that is not an L move is the
     // highest code below the current position that is not 2.  Lane (k mod 64)
     // keeps the k-th diagonal move; each full batch of 64 is stored at once.
     int i = n, j = m, k = 0;
     int vs = 0, vt = 0;
+    int wr0 = -1;                        // window's first row (0-based), -1: no window
+    uint32_t w0 = 0, w1 = 0, w2 = 0;     // this lane's words wlo, wlo + 1, wlo + 2 of row wr0 - lane
+    int wlo = 0;                         // this lane's first word index
+    auto load_window = [&]() {
+      wr0 = i - 1;
+      const int r = wr0 - lane;
+      w0 = w1 = w2 = 0;
+      wlo = 0;
+      if (r >= 0) {
+        const int l = r & 63;
+        const int wj = ((j + l) >> 4) - (l >> 4);
+        wlo = max(0, wj - 2);
+        const uint32_t *row = dirs + (int64_t)r * Wr;
+        if (kLds) {
+          w0 = row[wlo];
+          if (wlo + 1 < Wr) w1 = row[wlo + 1];
+          if (wlo + 2 < Wr) w2 = row[wlo + 2];
+        } else {
+          const volatile uint32_t *vrow = row;
+          w0 = vrow[wlo];
+          if (wlo + 1 < Wr) w1 = vrow[wlo + 1];
+          if (wlo + 2 < Wr) w2 = vrow[wlo + 2];
+        }
+      }
+    };
     while (i > 0 && j > 0) {
       const int l = (i - 1) & 63, st = j + l;
-      const int64_t widx = (int64_t)(i - 1) * Wr + ((st >> 4) - (l >> 4));
-      const uint32_t word =
-          (uint32_t)__builtin_amdgcn_readfirstlane((int)(kLds ? dirs[widx] : ((volatile const uint32_t *)dirs)[widx]));
+      const int wi = (st >> 4) - (l >> 4);
+      int q = wr0 - (i - 1);
+      int d = wr0 < 0 || q > 63 ? -1 : wi - __builtin_amdgcn_readlane(wlo, q);
+      if (d < 0) {
+        load_window();
+        q = 0;
+        d = wi - __builtin_amdgcn_readlane(wlo, 0);
+      }
+      const uint32_t word = (uint32_t)__builtin_amdgcn_readlane((int)(d == 0 ? w0 : (d == 1 ? w1 : w2)), q);
       const int pos = st & 15;
       const uint32_t notL = ~(word >> 1) & 0x55555555u & (0xFFFFFFFFu >> (30 - 2 * pos));
       if (notL == 0) {  // L moves down to the word's first step
         j -= min(pos + 1, j);
         continue;
       }
-      const int q = (31 - __builtin_clz(notL)) >> 1;
-      if (j - (pos - q) < 1) {  // the L run reaches column 0 first
+      const int qb = (31 - __builtin_clz(notL)) >> 1;
+      if (j - (pos - qb) < 1) {  // the L run reaches column 0 first
         j = 0;
         break;
       }
-      j -= pos - q;
-      if (((word >> (2 * q)) & 3u) == 0u) {
+      j -= pos - qb;
+      if (((word >> (2 * qb)) & 3u) == 0u) {
         if (lane == (k & 63)) {
           vs = i - 1;
           vt = j - 1;
@@ -1278,7 +1371,25 @@ __device__ __forceinline__ void nw_pair(const NwArgs &a, const PairDesc &d, int6
   }
 }
 
-// NPW pairs per workgroup, one wave each (waves never synchronise with each other).
+// A pair swept by one wave, strip after strip.
+template <bool kLds>
+__device__ __forceinline__ void nw_pair(const NwArgs &a, const PairDesc &d, int64_t p, uint32_t *dirs,
+                                        float *rowbuf) {
+  float hnm = 0.0f;
+  if (d.n > 0 && d.m > 0) {
+    const int nstrips = (d.n + 63) >> 6;
+    for (int s = 0; s < nstrips; s++) {
+      hnm = nw_strip(a, d, s, dirs, rowbuf, rowbuf, NwPipe{});
+      wave_sync_mem();
+    }
+  } else {
+    hnm = nw_boundary_only(d.n, d.m, a.gap);
+  }
+  nw_finish<kLds>(a, d, p, dirs, hnm);
+}
+
+// NPW pairs per workgroup, one wave each (waves never synchronise with each
+// other).  Large pairs (nw_is_big) are left to nw_big_kernel.
 template <int NPW>
 __global__ __launch_bounds__(64 * NPW) void nw_kernel(NwArgs a) {
   __shared__ uint32_t sdir_all[NPW][kDirLds];
@@ -1289,11 +1400,65 @@ __global__ __launch_bounds__(64 * NPW) void nw_kernel(NwArgs a) {
   uint32_t *sdir = sdir_all[wv];
   float *srow = srow_all[wv];
   const PairDesc d = a.descs[p];
+  if (nw_is_big(d.n)) return;
   if (d.dir_off < 0 && d.row_off < 0)
     nw_pair<true>(a, d, p, sdir, srow);
   else
     nw_pair<false>(a, d, p, d.dir_off < 0 ? sdir : a.dir_scratch + d.dir_off,
                    d.row_off < 0 ? srow : a.row_scratch + d.row_off);
+}
+
+// Large pairs: one workgroup of kNwBigWaves waves per pair.  Strip s is swept
+// by wave s mod W; its lane 0 reads the bottom row of strip s - 1 as that
+// strip publishes it (16 columns at a time, through global scratch with one
+// row per strip boundary), so the strips run as a pipeline lagging about one
+// block plus 64 steps behind each other.  Every wait is for a strip with a
+// smaller index, swept by a wave of the same (co-resident) workgroup, so the
+// pipeline always drains; each wait also ends after kNwWaitTicks (the pair is
+// then reported with no accepted pairs and a NaN score).  After the sweep,
+// wave 0 traces back.
+__global__ __launch_bounds__(64 * kNwBigWaves) void nw_big_kernel(NwArgs a) {
+  __shared__ int64_t prog[kNwBigWaves];
+  __shared__ int abort_flag;
+  __shared__ float s_hnm;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  for (int64_t bi = blockIdx.x; bi < a.n_big; bi += gridDim.x) {
+    const int64_t p = a.big[bi];
+    const PairDesc d = a.descs[p];
+    if (threadIdx.x < kNwBigWaves) prog[threadIdx.x] = (int64_t)(-1ll * (1ll << 32));  // strip -1, 0 columns
+    if (threadIdx.x == 0) {
+      abort_flag = 0;
+      s_hnm = 0.0f;
+    }
+    __syncthreads();
+    uint32_t *dirs = a.dir_scratch + d.dir_off;
+    float *rows = a.row_scratch + d.row_off;  // bottom row of strip s at rows + s (m + 1)
+    const int nstrips = (d.n + 63) >> 6;
+    const NwPipe pp{prog, kNwBigWaves, &abort_flag};
+    if (d.m <= 0) {  // no target sentence: the boundary alone
+      if (threadIdx.x == 0) s_hnm = nw_boundary_only(d.n, d.m, a.gap);
+    } else
+    for (int s = wv; s < nstrips; s += kNwBigWaves) {
+      const float h = nw_strip(a, d, s, dirs, s > 0 ? rows + (int64_t)(s - 1) * (d.m + 1) : nullptr,
+                               s + 1 < nstrips ? rows + (int64_t)s * (d.m + 1) : nullptr, pp);
+      if (s == nstrips - 1 && lane == 0) s_hnm = h;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    if (wv == 0) {
+      if (abort_flag) {
+        if (lane == 0) {
+          a.counts[p] = 0;
+          a.align[a.pair_base + p] = __int_as_float(0x7fc00000);
+          if (a.n_moves) a.n_moves[a.pair_base + p] = 0;
+        }
+      } else {
+        nw_finish<false>(a, d, p, dirs, s_hnm);
+      }
+    }
+    __syncthreads();
+  }
 }
 
 // ----------------------------------------------------------- compaction
@@ -1470,6 +1635,12 @@ hipError_t launch_similarity(const SimArgs &a, int grid, int variant, hipStream_
 
 hipError_t launch_nw(const NwArgs &a, int pairs_per_group, hipStream_t st) {
   if (a.n_pairs <= 0) return hipSuccess;
+  if (a.n_big > 0) {
+    hipLaunchKernelGGL(nw_big_kernel, dim3((unsigned)std::min<int64_t>(a.n_big, 1024)), dim3(64 * kNwBigWaves), 0, st,
+                       a);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   switch (pairs_per_group) {
     case 1:
       hipLaunchKernelGGL(nw_kernel<1>, dim3((unsigned)a.n_pairs), dim3(64), 0, st, a);

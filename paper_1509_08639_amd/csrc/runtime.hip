@@ -101,15 +101,25 @@ void HostBuf::release() {
 
 // ------------------------------------------------------------------ plan
 // Per-pair requirement in workspace bytes (score block, scratch, slots).
-static inline bool nw_needs_global_dirs(int64_t n, int64_t m) { return n * nw_dir_row_words(m) > kDirLds; }
-static inline bool nw_needs_global_row(int64_t n, int64_t m) { return n > 64 && m + 1 > kRowLds; }
+static inline bool nw_needs_global_dirs(int64_t n, int64_t m) {
+  return nw_is_big(n) || n * nw_dir_row_words(m) > kDirLds;
+}
+// boundary-row floats in global scratch: one row per strip boundary for the
+// pipelined sweep of a large pair, one reused row for a one-wave sweep whose
+// row does not fit LDS
+static inline int64_t nw_global_row_floats(int64_t n, int64_t m) {
+  if (nw_is_big(n)) return ((n + 63) / 64 - 1) * (m + 1);
+  return (n > 64 && m + 1 > kRowLds) ? m + 1 : 0;
+}
+static inline bool nw_needs_global_row(int64_t n, int64_t m) { return nw_global_row_floats(n, m) > 0; }
 
 size_t pair_bytes(int64_t n, int64_t m) {
   size_t b = sizeof(PairDesc) + 4 /*count*/ + 8 /*moves off*/;
   b += (size_t)((n + kMinItemRows - 1) / kMinItemRows) * sizeof(SimItem);  // bound over item sizes
   b += (size_t)score_slots(n, m) * 4;
   if (nw_needs_global_dirs(n, m)) b += (size_t)(n * nw_dir_row_words(m)) * 4;
-  if (nw_needs_global_row(n, m)) b += (size_t)(m + 1) * 4;
+  b += (size_t)nw_global_row_floats(n, m) * 4;
+  if (nw_is_big(n)) b += 4;  // its entry in the list of large pairs
   b += (size_t)std::min(n, m) * 12;
   return b;
 }
@@ -127,13 +137,15 @@ ym_status Chunk::layout(const int64_t *sdo, const int64_t *tdo, int64_t p0_, int
   dir_words = 0;
   row_floats = 0;
   slots = 0;
+  n_big = 0;
   for (int64_t p = p0; p < p1; p++) {
     const int64_t n = sdo[p + 1] - sdo[p], m = tdo[p + 1] - tdo[p];
     if (n > 0 && m > 0) n_items += (n + item_rows - 1) / item_rows;
     cells += n * m;
     s_slots += score_slots(n, m);
     if (nw_needs_global_dirs(n, m)) dir_words += n * nw_dir_row_words(m);
-    if (nw_needs_global_row(n, m)) row_floats += m + 1;
+    row_floats += nw_global_row_floats(n, m);
+    if (nw_is_big(n)) n_big++;
     slots += std::min(n, m);
   }
   size_t o = 0;
@@ -157,9 +169,11 @@ ym_status Chunk::layout(const int64_t *sdo, const int64_t *tdo, int64_t p0_, int
   o = align256(o + (size_t)np * 4);
   off_moves_off = o;
   o = align256(o + (size_t)np * 8);
+  off_big = o;
+  o = align256(o + (size_t)std::max<int64_t>(n_big, 1) * 4);
   bytes = o;
   host_bytes = align256((size_t)np * sizeof(PairDesc)) + align256((size_t)std::max<int64_t>(n_items, 1) * sizeof(SimItem)) +
-               align256((size_t)np * 8);
+               align256((size_t)np * 8) + align256((size_t)std::max<int64_t>(n_big, 1) * 4);
   return YM_OK;
 }
 
@@ -169,7 +183,8 @@ void Chunk::fill_host(const int64_t *sdo, const int64_t *tdo, char *host) const 
   SimItem *items = (SimItem *)(host + align256((size_t)np * sizeof(PairDesc)));
   int64_t *moff = (int64_t *)(host + align256((size_t)np * sizeof(PairDesc)) +
                               align256((size_t)std::max<int64_t>(n_items, 1) * sizeof(SimItem)));
-  int64_t s_off = 0, rm_off = 0, out_off = 0, dir_off = 0, row_off = 0, mv = 0, it = 0;
+  int32_t *big = (int32_t *)((char *)moff + align256((size_t)np * 8));
+  int64_t s_off = 0, rm_off = 0, out_off = 0, dir_off = 0, row_off = 0, mv = 0, it = 0, nb = 0;
   for (int64_t p = p0; p < p1; p++) {
     const int64_t n = sdo[p + 1] - sdo[p], m = tdo[p + 1] - tdo[p];
     PairDesc &d = descs[p - p0];
@@ -188,10 +203,11 @@ void Chunk::fill_host(const int64_t *sdo, const int64_t *tdo, char *host) const 
     }
     if (nw_needs_global_row(n, m)) {
       d.row_off = row_off;
-      row_off += m + 1;
+      row_off += nw_global_row_floats(n, m);
     } else {
       d.row_off = -1;
     }
+    if (nw_is_big(n)) big[nb++] = (int32_t)(p - p0);
     if (n > 0 && m > 0)
       for (int64_t i0 = 0; i0 < n; i0 += item_rows) {
         SimItem &x = items[it++];
@@ -527,6 +543,8 @@ ym_status run_chunk(ym_ctx *c, const ym_lexicon *L, const DevBatch &b, const ym_
       (e = hipMemcpyAsync(ws + ch.off_items, hp + dsz, isz, hipMemcpyHostToDevice, st)) != hipSuccess ||
       (e = hipMemcpyAsync(ws + ch.off_moves_off, hp + dsz + isz, align256((size_t)ch.np * 8), hipMemcpyHostToDevice, st)) !=
           hipSuccess ||
+      (ch.n_big > 0 && (e = hipMemcpyAsync(ws + ch.off_big, hp + dsz + isz + align256((size_t)ch.np * 8),
+                                           (size_t)ch.n_big * 4, hipMemcpyHostToDevice, st)) != hipSuccess) ||
       (!stg->caller_syncs && (e = hipEventRecord(stg->done, st)) != hipSuccess))
     return hip_fail(e, "plan upload");
 
@@ -586,6 +604,8 @@ ym_status run_chunk(ym_ctx *c, const ym_lexicon *L, const DevBatch &b, const ym_
   n.pair_base = ch.p0;
   n.moves = dbg ? dbg->moves_dev : nullptr;
   n.moves_off = (const int64_t *)(ws + ch.off_moves_off);
+  n.big = (const int32_t *)(ws + ch.off_big);
+  n.n_big = ch.n_big;
   n.n_moves = dbg ? dbg->n_moves_dev : nullptr;
   if (n.moves) n.moves += dbg->moves_base;
   {

@@ -36,6 +36,11 @@ static_assert((1 << kLogUcap) == kUcap, "hash capacity");
 // and a row's m cells span at most ceil(m/16) + 1 words.
 __host__ __device__ constexpr int64_t nw_dir_row_words(int64_t m) { return (m + 15) / 16 + 1; }
 
+// Pairs of at least kNwBigStrips strips of 64 rows are swept by a workgroup of
+// kNwBigWaves waves (strips pipelined over the waves); smaller ones by one wave.
+constexpr int kNwBigStrips = 8, kNwBigWaves = 16;
+__host__ __device__ constexpr bool nw_is_big(int64_t n) { return (n + 63) / 64 >= kNwBigStrips; }
+
 // Score layout of one n x m block: rows in strips of 64 (the last one has
 // R = n - 64 (strips - 1) rows); inside a strip, anti-diagonal t = l + c is a
 // row of R slots and cell (l, c) sits at t * R + l.  A strip holds
@@ -105,6 +110,8 @@ struct NwArgs {
   int32_t *counts;      // [n_pairs] accepted pairs
   float *align;         // [n_pairs] H[n][m] (global pair index = pair_base + local)
   int64_t pair_base;
+  const int32_t *big;   // [n_big] local indices of the large pairs (nw_is_big)
+  int64_t n_big;
   char *moves;          // optional: forward paths
   const int64_t *moves_off;  // [n_pairs] (local) offsets into moves
   int32_t *n_moves;     // optional [n_pairs] (global index)

@@ -89,7 +89,10 @@ def _nw_cases():
     r = np.random.default_rng(5)
     mats = []
     for (n, m) in [(1, 1), (0, 5), (6, 0), (0, 0), (3, 7), (64, 64), (65, 63), (127, 129), (200, 200),
-                   (40, 45), (300, 17), (17, 300), (130, 600), (70, 520), (1000, 1100)]:
+                   (40, 45), (300, 17), (17, 300), (130, 600), (70, 520), (1000, 1100),
+                   # pipelined sweep of large pairs: 8 strips (last of one row), 8 full, 17 strips
+                   # (more strips than waves), a single target column, no target sentence
+                   (449, 37), (512, 70), (1025, 90), (1100, 1), (700, 0), (1090, 3)]:
         mats.append(r.random((n, m)).astype(np.float32))
     # dyadic ties everywhere
     mats.append((r.integers(0, 3, (90, 77)) / 4.0).astype(np.float32))
