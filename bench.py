@@ -204,6 +204,8 @@ def main():
     ap.add_argument("--per-pair-sample", type=int, default=1000, help="pairs timed in the plain per-pair form")
     ap.add_argument("--serve-seconds", type=float, default=5.0, help="length of the served arrival trace (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=2000.0, help="Poisson arrival rate of the served trace")
+    ap.add_argument("--max-pairs", type=int, default=100000,
+                    help="pairs generated for a workload larger than this (its first pairs; 0: all)")
     ap.add_argument("--autotune-pairs", type=int, default=10000,
                     help="sample size for the autotuner before the timed region (0: default configuration)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -236,7 +238,8 @@ def main():
     log(f"[bench] generating workload {cfg.name} ...")
     t = time.time()
     lex = synth.make_lexicon(cfg)
-    corpus = synth.generate(cfg, lex)
+    n_gen = min(cfg.n_pairs, args.max_pairs) if args.max_pairs > 0 else cfg.n_pairs
+    corpus = synth.generate(cfg, lex, pair_ids=np.arange(n_gen)) if n_gen < cfg.n_pairs else synth.generate(cfg, lex)
     w = synth.weights(cfg.seed)
     gap, tau = np.float32(-0.2), np.float32(0.5)
     st = workload_stats(corpus, lex)
@@ -363,7 +366,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": cfg.name, "n_pairs": corpus.n_pairs, "cells": cells,
+        "config": {"workload": cfg.name, "n_pairs": corpus.n_pairs, "workload_pairs": cfg.n_pairs, "cells": cells,
                    "src_tokens": st["src_tokens"], "tgt_tokens": st["tgt_tokens"], "gap": float(gap),
                    "threshold": float(tau), "parallelism": "single GPU", "tuning": tuning},
         "gcups": gcups,

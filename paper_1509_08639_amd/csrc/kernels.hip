@@ -440,8 +440,8 @@ __global__ __launch_bounds__(kSimThreads, 3) void sim_kernel(SimArgs a) {
                 if (l) atomicOr(&Mx[2 * l], bits);
               }
             } else {
-              const int l0 = u2_lid(uent, t4.x), l1 = u2_lid(uent, t4.y), l2 = u2_lid(uent, t4.z),
-                        l3 = u2_lid(uent, t4.w);
+              const int4 lid = u2_lid4(uent, t4);
+              const int l0 = lid.x, l1 = lid.y, l2 = lid.z, l3 = lid.w;
               if (l0) atomicOr(&Mx[2 * l0], bits);
               if (l1) atomicOr(&Mx[2 * l1], bits);
               if (l2) atomicOr(&Mx[2 * l2], bits);
@@ -461,11 +461,15 @@ __global__ __launch_bounds__(kSimThreads, 3) void sim_kernel(SimArgs a) {
               acc |= (w0 | w1) | (w2 | w3);
             }
           }
-          if (maxb > kRegTok) {  // sentences beyond 32 tokens: the rest straight from LDS
-            for (int k2 = kRegTok; k2 < bl; k2++) {
-              const uint32_t w = Mx[2 * tp[k2]];
-              mt += w >> 31;
-              acc |= w;
+          // sentences beyond 32 tokens: the rest straight from LDS, four ids per
+          // read (sentences are padded to a multiple of 4 with id 0)
+          for (int k2 = kRegTok; k2 < maxb; k2 += 4) {
+            if (k2 < bl) {
+              const uint2 ids = *reinterpret_cast<const uint2 *>(tp + k2);
+              const uint32_t w0 = Mx[2 * (ids.x & 0xFFFFu)], w1 = Mx[2 * (ids.x >> 16)];
+              const uint32_t w2 = Mx[2 * (ids.y & 0xFFFFu)], w3 = Mx[2 * (ids.y >> 16)];
+              mt += ((w0 >> 31) + (w1 >> 31)) + ((w2 >> 31) + (w3 >> 31));
+              acc |= (w0 | w1) | (w2 | w3);
             }
           }
           ms_acc += __popc(acc & ~kHitBit);
@@ -540,13 +544,17 @@ __global__ __launch_bounds__(kSimThreads, 3) void sim_kernel(SimArgs a) {
             }
           }
         }
-        if (maxb > kRegTok) {
-          for (int k2 = kRegTok; k2 < bl; k2++) {
-            const uint2 w = *reinterpret_cast<const uint2 *>(Mx + 2 * tp[k2]);
-            mt0 += w.x >> 31;
-            acc0 |= w.x;
-            mt1 += w.y >> 31;
-            acc1 |= w.y;
+        for (int k2 = kRegTok; k2 < maxb; k2 += 4) {  // beyond 32 tokens, four ids per read
+          if (k2 < bl) {
+            const uint2 ids = *reinterpret_cast<const uint2 *>(tp + k2);
+            const uint2 w0 = *reinterpret_cast<const uint2 *>(Mx + 2 * (ids.x & 0xFFFFu));
+            const uint2 w1 = *reinterpret_cast<const uint2 *>(Mx + 2 * (ids.x >> 16));
+            const uint2 w2 = *reinterpret_cast<const uint2 *>(Mx + 2 * (ids.y & 0xFFFFu));
+            const uint2 w3 = *reinterpret_cast<const uint2 *>(Mx + 2 * (ids.y >> 16));
+            mt0 += ((w0.x >> 31) + (w1.x >> 31)) + ((w2.x >> 31) + (w3.x >> 31));
+            acc0 |= (w0.x | w1.x) | (w2.x | w3.x);
+            mt1 += ((w0.y >> 31) + (w1.y >> 31)) + ((w2.y >> 31) + (w3.y >> 31));
+            acc1 |= (w0.y | w1.y) | (w2.y | w3.y);
           }
         }
         wave_sync();

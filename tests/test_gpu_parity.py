@@ -281,3 +281,22 @@ def test_similarity_variants_agree(ym, O, seed):
         cx.close()
     for a, b in zip(*outs):
         assert np.array_equal(a, b)
+
+
+def test_scale_workload_sample(ym, ctx, O):
+    """Pairs of the 1M-pair scale workload (3-60 token sentences, Zipf 1.05,
+    1-4 translations per key): rows longer than 31 tokens take the one-row
+    path; the mined sets match the oracle."""
+    cfg = synth.CONFIGS[4]
+    lex = synth.make_lexicon(cfg)
+    c = synth.generate(cfg, lex, pair_ids=np.arange(0, 1000000, 20000))
+    w = synth.weights(cfg.seed)
+    L = ctx.lexicon(lex.src_ids, lex.off, lex.tgt_ids)
+    got = ym.mine(ctx, L, c, w, -0.2, 0.5)
+    OL = O.lexicon(lex.src_ids, lex.off, lex.tgt_ids)
+    want = O.mine(OL, c, w, F32(-0.2), F32(0.5))
+    S, _, _ = ym.similarity(ctx, L, c, w)
+    ties = parity.compare_mined(O, OL, c, w, F32(-0.2), F32(0.5), got, want, S)
+    assert len(ties) <= 2, ties
+    lens = np.diff(c.src_sent_off)
+    assert lens.max() > 31  # the long-row path is exercised
