@@ -1403,8 +1403,9 @@ __global__ __launch_bounds__(64 * NPW) void nw_kernel(NwArgs a) {
   __shared__ uint32_t sdir_all[NPW][kDirLds];
   __shared__ float srow_all[NPW][kRowLds];
   const int wv = NPW == 1 ? 0 : __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t p = (int64_t)blockIdx.x * NPW + wv;
-  if (p >= a.n_pairs) return;
+  const int64_t slot = (int64_t)blockIdx.x * NPW + wv;
+  if (slot >= a.n_pairs) return;
+  const int64_t p = a.order[slot];
   uint32_t *sdir = sdir_all[wv];
   float *srow = srow_all[wv];
   const PairDesc d = a.descs[p];

@@ -171,9 +171,12 @@ ym_status Chunk::layout(const int64_t *sdo, const int64_t *tdo, int64_t p0_, int
   o = align256(o + (size_t)np * 8);
   off_big = o;
   o = align256(o + (size_t)std::max<int64_t>(n_big, 1) * 4);
+  off_order = o;
+  o = align256(o + (size_t)std::max<int64_t>(np, 1) * 4);
   bytes = o;
   host_bytes = align256((size_t)np * sizeof(PairDesc)) + align256((size_t)std::max<int64_t>(n_items, 1) * sizeof(SimItem)) +
-               align256((size_t)np * 8) + align256((size_t)std::max<int64_t>(n_big, 1) * 4);
+               align256((size_t)np * 8) + align256((size_t)std::max<int64_t>(n_big, 1) * 4) +
+               align256((size_t)std::max<int64_t>(np, 1) * 4);
   return YM_OK;
 }
 
@@ -184,6 +187,7 @@ void Chunk::fill_host(const int64_t *sdo, const int64_t *tdo, char *host) const 
   int64_t *moff = (int64_t *)(host + align256((size_t)np * sizeof(PairDesc)) +
                               align256((size_t)std::max<int64_t>(n_items, 1) * sizeof(SimItem)));
   int32_t *big = (int32_t *)((char *)moff + align256((size_t)np * 8));
+  int32_t *order = (int32_t *)((char *)big + align256((size_t)std::max<int64_t>(n_big, 1) * 4));
   int64_t s_off = 0, rm_off = 0, out_off = 0, dir_off = 0, row_off = 0, mv = 0, it = 0, nb = 0;
   for (int64_t p = p0; p < p1; p++) {
     const int64_t n = sdo[p + 1] - sdo[p], m = tdo[p + 1] - tdo[p];
@@ -222,6 +226,17 @@ void Chunk::fill_host(const int64_t *sdo, const int64_t *tdo, char *host) const 
     rm_off += n * m;
     out_off += std::min(n, m);
   }
+  // the largest pairs first in the NW launch, and the largest similarity
+  // items (rows x target sentences) first, so each kernel's last workgroups
+  // are short ones
+  for (int64_t q = 0; q < np; q++) order[q] = (int32_t)q;
+  std::stable_sort(order, order + np, [&](int32_t x, int32_t y) {
+    return (int64_t)descs[x].n * descs[x].m > (int64_t)descs[y].n * descs[y].m;
+  });
+  std::stable_sort(items, items + it, [&](const SimItem &x, const SimItem &y) {
+    const int64_t wx = (int64_t)(x.i1 - x.i0) * descs[x.pair].m, wy = (int64_t)(y.i1 - y.i0) * descs[y.pair].m;
+    return wx > wy;
+  });
 }
 
 }  // namespace ym
@@ -545,6 +560,9 @@ ym_status run_chunk(ym_ctx *c, const ym_lexicon *L, const DevBatch &b, const ym_
           hipSuccess ||
       (ch.n_big > 0 && (e = hipMemcpyAsync(ws + ch.off_big, hp + dsz + isz + align256((size_t)ch.np * 8),
                                            (size_t)ch.n_big * 4, hipMemcpyHostToDevice, st)) != hipSuccess) ||
+      (e = hipMemcpyAsync(ws + ch.off_order,
+                          hp + dsz + isz + align256((size_t)ch.np * 8) + align256((size_t)std::max<int64_t>(ch.n_big, 1) * 4),
+                          (size_t)ch.np * 4, hipMemcpyHostToDevice, st)) != hipSuccess ||
       (!stg->caller_syncs && (e = hipEventRecord(stg->done, st)) != hipSuccess))
     return hip_fail(e, "plan upload");
 
@@ -605,6 +623,7 @@ ym_status run_chunk(ym_ctx *c, const ym_lexicon *L, const DevBatch &b, const ym_
   n.moves = dbg ? dbg->moves_dev : nullptr;
   n.moves_off = (const int64_t *)(ws + ch.off_moves_off);
   n.big = (const int32_t *)(ws + ch.off_big);
+  n.order = (const int32_t *)(ws + ch.off_order);
   n.n_big = ch.n_big;
   n.n_moves = dbg ? dbg->n_moves_dev : nullptr;
   if (n.moves) n.moves += dbg->moves_base;

@@ -111,6 +111,7 @@ struct NwArgs {
   float *align;         // [n_pairs] H[n][m] (global pair index = pair_base + local)
   int64_t pair_base;
   const int32_t *big;   // [n_big] local indices of the large pairs (nw_is_big)
+  const int32_t *order; // [n_pairs] local pair indices, largest first (launch order of the one-wave sweeps)
   int64_t n_big;
   char *moves;          // optional: forward paths
   const int64_t *moves_off;  // [n_pairs] (local) offsets into moves

@@ -54,7 +54,7 @@ struct Chunk {
   int64_t p0 = 0, p1 = 0, np = 0, n_items = 0, cells = 0, s_slots = 0, dir_words = 0, row_floats = 0, slots = 0,
           n_big = 0;
   size_t off_descs = 0, off_items = 0, off_S = 0, off_dirs = 0, off_rows = 0, off_ssrc = 0, off_stgt = 0,
-         off_sscore = 0, off_counts = 0, off_moves_off = 0, off_big = 0, bytes = 0, host_bytes = 0;
+         off_sscore = 0, off_counts = 0, off_moves_off = 0, off_big = 0, off_order = 0, bytes = 0, host_bytes = 0;
   int item_rows = kItemRows;  // source sentences per similarity work item
   ym_status layout(const int64_t *sdo, const int64_t *tdo, int64_t p0, int64_t p1, int item_rows);
   void fill_host(const int64_t *sdo, const int64_t *tdo, char *host) const;
