@@ -102,25 +102,46 @@ __global__ __launch_bounds__(256) void lex_insert_kernel(const int32_t *keys, co
 }
 
 // Translations of every source token of a batch, resolved once per call
-// (the slot's record; -1 x 4 for ids that are not keys).
+// (the slot's record; -1 x 4 for ids that are not keys).  Each thread takes
+// four tokens 256 apart, so four independent probe chains are in flight.
+constexpr int kTransPerThread = 4;
 __global__ __launch_bounds__(256) void translate_kernel(const int32_t *tok, int64_t n, LexDev L, int4 *out) {
-  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (k >= n) return;
-  const int32_t x = tok[k];
-  int4 r = make_int4(-1, -1, -1, -1);
-  if (x >= 0) {
-    uint32_t h = hash32(x) >> L.shift;
-    for (;;) {
-      const int4 s = L.slots[2 * h], t = L.slots[2 * h + 1];
-      if (s.x == x) {
-        r = t;
-        break;
-      }
-      if (s.x == kEmpty) break;
-      h = (h + 1) & L.mask;
+  const int64_t base = (int64_t)blockIdx.x * (256 * kTransPerThread) + threadIdx.x;
+  int32_t x[kTransPerThread];
+  uint32_t h[kTransPerThread];
+  int4 s[kTransPerThread], t[kTransPerThread];
+  bool more[kTransPerThread];
+#pragma unroll
+  for (int u = 0; u < kTransPerThread; u++) {
+    const int64_t k = base + 256 * u;
+    x[u] = k < n ? tok[k] : -1;
+  }
+#pragma unroll
+  for (int u = 0; u < kTransPerThread; u++) {
+    h[u] = hash32(x[u]) >> L.shift;
+    if (x[u] >= 0) {
+      s[u] = L.slots[2 * h[u]];
+      t[u] = L.slots[2 * h[u] + 1];
+    } else {
+      s[u] = make_int4(kEmpty, 0, 0, 0);
+      t[u] = make_int4(-1, -1, -1, -1);
     }
   }
-  out[k] = r;
+#pragma unroll
+  for (int u = 0; u < kTransPerThread; u++) {
+    more[u] = x[u] >= 0 && s[u].x != x[u] && s[u].x != kEmpty;
+    while (more[u]) {  // collision: next slot
+      h[u] = (h[u] + 1) & L.mask;
+      s[u] = L.slots[2 * h[u]];
+      t[u] = L.slots[2 * h[u] + 1];
+      more[u] = s[u].x != x[u] && s[u].x != kEmpty;
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kTransPerThread; u++) {
+    const int64_t k = base + 256 * u;
+    if (k < n) out[k] = (x[u] >= 0 && s[u].x == x[u]) ? t[u] : make_int4(-1, -1, -1, -1);
+  }
 }
 
 // ---------------------------------------------------------- LDS id table
@@ -1623,7 +1644,8 @@ hipError_t launch_lex_insert(const int32_t *keys, const int32_t *cnts, const int
 
 hipError_t launch_translate(const int32_t *tok, int64_t n, const LexDev &L, int4 *out, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(translate_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, tok, n, L, out);
+  hipLaunchKernelGGL(translate_kernel, dim3((unsigned)((n + 256 * kTransPerThread - 1) / (256 * kTransPerThread))),
+                     dim3(256), 0, st, tok, n, L, out);
   return hipGetLastError();
 }
 
