@@ -419,18 +419,30 @@ __global__ __launch_bounds__(kSimThreads, 3) void sim_kernel(SimArgs a) {
       const int ng = (min(maxb, kRegTok) + 3) >> 2;
       const int nq4 = (nlid + 1) >> 1;  // 16-byte stores covering the chunk's entries
 
-      // Score of cell (i, j0 + lane) from its counts; stored one call later
-      // (two pending slots, one per half), so the table read is not waited
-      // for before the next rows' work.
-      float *pend_dst0 = nullptr, *pend_dst1 = nullptr;
-      float pend_sv0 = 0.0f, pend_sv1 = 0.0f;
-      auto score_cell = [&](int i, int ai, uint32_t ms, uint32_t mt, float *&dst) -> float {
-        dst = nullptr;
+      // Score of cell (i, j0 + lane) from its counts, and its offset in the
+      // pair's score block (-1: no cell).  The two-row steps store their
+      // scores two steps later (two sets of pending scores, one per call site
+      // of the unrolled loop), so the table reads are not waited for while
+      // the next rows are worked on.
+      float *const Sb = a.S + d.s_off;
+      struct Pend {
+        int o0 = -1, o1 = -1;
+        float v0 = 0.0f, v1 = 0.0f;
+      };
+      auto flush = [&](Pend &q) {
+        if (q.o0 >= 0) Sb[q.o0] = q.v0;
+        if (q.o1 >= 0) Sb[q.o1] = q.v1;
+      };
+      auto score_cell = [&](int i, int ai, uint32_t ms, uint32_t mt, int &off) -> float {
+        // the table read is issued by every lane (clamped index), so no branch
+        // hides it from the wait-count bookkeeping
+        const int ca = min(ai, kTabLen - 1), cb = min(bl, kTabLen - 1);
+        const int cs = min((int)ms, kTabLen - 1), ct = min((int)mt, kTabLen - 1);
+        float sv = a.table[((ca * kTabLen + cb) * kTabLen + cs) * kTabLen + ct];
+        off = -1;
         if (!jok) return 0.0f;
-        const float sv = (ai < kTabLen && bl < kTabLen)
-                             ? a.table[((ai * kTabLen + bl) * kTabLen + (int)ms) * kTabLen + (int)mt]
-                             : score_direct(a.w0, a.w1, a.w2, a.w3, (int)ms, ai, (int)mt, bl);
-        dst = a.S + d.s_off + score_pos(i, j0 + lane, n, m);
+        if (ai >= kTabLen || bl >= kTabLen) sv = score_direct(a.w0, a.w1, a.w2, a.w3, (int)ms, ai, (int)mt, bl);
+        off = (int)score_pos(i, j0 + lane, n, m);
         if (a.ms_out) {
           const int64_t cell = d.rm_off + (int64_t)i * m + j0 + lane;
           a.ms_out[cell] = (int)ms;
@@ -499,9 +511,9 @@ __global__ __launch_bounds__(kSimThreads, 3) void sim_kernel(SimArgs a) {
           for (int k2 = lane; k2 < nq4; k2 += 64) reinterpret_cast<uint4 *>(Mx)[k2] = make_uint4(0, 0, 0, 0);
           wave_sync();
         }
-        float *dst;
-        const float sv = score_cell(i, ai, ms_acc, mt_acc, dst);
-        if (dst) *dst = sv;
+        int off;
+        const float sv = score_cell(i, ai, ms_acc, mt_acc, off);
+        if (off >= 0) Sb[off] = sv;
       };
 
       // Two rows at a time (both of at most 31 tokens): lanes 0-31 hold the
@@ -515,9 +527,12 @@ __global__ __launch_bounds__(kSimThreads, 3) void sim_kernel(SimArgs a) {
         const int n1 = k + 1 < nrows ? __builtin_amdgcn_readlane(rlen, min(k + 1, 63)) : 0;
         const int q = lane & 31, len = lane < 32 ? n0 : n1;
         const bool ok = q < len && len <= kPosBits;
-        return ok ? a.trans[(lane < 32 ? b0 : b1) + q] : make_int4(-1, -1, -1, -1);
+        // every lane reads (a valid token's record: clamped), then keeps it or not
+        const int64_t at = ok ? (lane < 32 ? b0 : b1) + q : 0;
+        const int4 r = a.trans[at];
+        return ok ? r : make_int4(-1, -1, -1, -1);
       };
-      auto pair_rows = [&](const int k, const int4 cur) {
+      auto pair_rows = [&](const int k, const int4 cur, Pend &pend) {
         const int ai0 = __builtin_amdgcn_readlane(rlen, k);
         const bool has1 = k + 1 < nrows;
         const int ai1 = has1 ? __builtin_amdgcn_readlane(rlen, k + 1) : 0;
@@ -594,27 +609,27 @@ __global__ __launch_bounds__(kSimThreads, 3) void sim_kernel(SimArgs a) {
         }
         wave_sync();
         const int i = it.i0 + wv + kSimWaves * k;
-        float *dst0, *dst1 = nullptr;
-        const float sv0 = score_cell(i, ai0, __popc(acc0 & ~kHitBit), mt0, dst0);
+        int off0, off1 = -1;
+        const float sv0 = score_cell(i, ai0, __popc(acc0 & ~kHitBit), mt0, off0);
         float sv1 = 0.0f;
-        if (has1) sv1 = score_cell(i + kSimWaves, ai1, __popc(acc1 & ~kHitBit), mt1, dst1);
-        if (pend_dst0) *pend_dst0 = pend_sv0;
-        if (pend_dst1) *pend_dst1 = pend_sv1;
-        pend_dst0 = dst0;
-        pend_sv0 = sv0;
-        pend_dst1 = dst1;
-        pend_sv1 = sv1;
+        if (has1) sv1 = score_cell(i + kSimWaves, ai1, __popc(acc1 & ~kHitBit), mt1, off1);
+        flush(pend);  // this call site's scores of two steps ago
+        pend.o0 = off0;
+        pend.v0 = sv0;
+        pend.o1 = off1;
+        pend.v1 = sv1;
       };
       int4 bufA = fetch2(0), bufB;
+      Pend qa, qb;
       for (int k = 0; k < nrows; k += 4) {
         bufB = fetch2(k + 2);
-        pair_rows(k, bufA);
+        pair_rows(k, bufA, qa);
         if (k + 2 >= nrows) break;
         bufA = fetch2(k + 4);
-        pair_rows(k + 2, bufB);
+        pair_rows(k + 2, bufB, qb);
       }
-      if (pend_dst0) *pend_dst0 = pend_sv0;
-      if (pend_dst1) *pend_dst1 = pend_sv1;
+      flush(qa);
+      flush(qb);
       __syncthreads();
       j0 = j1;
     }
