@@ -208,6 +208,11 @@ __device__ __forceinline__ int block_excl_sum256(int v, int *sh, int *total) {
 
 __device__ __forceinline__ int64_t clamp64(int64_t v, int64_t lo, int64_t hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
+__device__ __forceinline__ float shift_up_one_lane(float v) {
+  // wave_shr:1 -- lane l receives lane l-1's value (lane 0 keeps its own)
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x138, 0xF, 0xF, false));
+}
+
 // offset of score (i, c) inside its pair's block (layout: score_slots)
 __device__ __forceinline__ int64_t score_pos(int i, int c, int n, int m) {
   const int s = i >> 6, l = i & 63;
@@ -325,12 +330,15 @@ __global__ __launch_bounds__(kSimThreads, 3) void sim_kernel(SimArgs a) {
     if (m <= 0 || it.i1 <= it.i0) continue;
     const int64_t *toffs = a.tgt_sent_off + d.tgt_sent0;
     const int64_t *soffs = a.src_sent_off + d.src_sent0;
-    // this wave's source rows and their token ranges (lane k: row k)
-    const int nrows = max(0, (it.i1 - it.i0 - wv + kSimWaves - 1) / kSimWaves);
+    // this wave's source rows and their token ranges (lane k: row k).  Wave
+    // wv takes rows i0 + 2 wv + 8 q and the row after (q = 0, 1, ...), so the
+    // two rows of a step are adjacent (items start on 64-row strips).
+    auto row_of = [&](int k) { return it.i0 + 2 * wv + 2 * kSimWaves * (k >> 1) + (k & 1); };
+    const int nrows = 2 * ((it.i1 - it.i0) / (2 * kSimWaves)) + min(2, max(0, (it.i1 - it.i0) % (2 * kSimWaves) - 2 * wv));
     int64_t rsb = 0;
     int rlen = 0;
     if (lane < nrows) {
-      const int ii = it.i0 + wv + kSimWaves * lane;
+      const int ii = row_of(lane);
       rsb = clamp64(soffs[ii], 0, a.n_src_tok);
       const int64_t se = clamp64(soffs[ii + 1], rsb, a.n_src_tok);
       rlen = (int)min(se - rsb, (int64_t)0x7fffffff);
@@ -425,13 +433,22 @@ __global__ __launch_bounds__(kSimThreads, 3) void sim_kernel(SimArgs a) {
       // of the unrolled loop), so the table reads are not waited for while
       // the next rows are worked on.
       float *const Sb = a.S + d.s_off;
+      // A step's two rows i, i + 1 lie in one strip, where cell (i + 1, c - 1)
+      // follows cell (i, c): lane c stores both as one 8-byte store (strips of
+      // an even row count; the pair's block starts 16-byte aligned).
       struct Pend {
-        int o0 = -1, o1 = -1;
-        float v0 = 0.0f, v1 = 0.0f;
+        int o0 = -1, oB = -1;  // o0: cell (i, c), paired with (i + 1, c - 1); oB: (i + 1, c) alone
+        float v0 = 0.0f, vl = 0.0f, vB = 0.0f;
+        bool paired = false;
       };
       auto flush = [&](Pend &q) {
-        if (q.o0 >= 0) Sb[q.o0] = q.v0;
-        if (q.o1 >= 0) Sb[q.o1] = q.v1;
+        if (q.o0 >= 0) {
+          if (q.paired)
+            *reinterpret_cast<float2 *>(Sb + q.o0) = make_float2(q.v0, q.vl);
+          else
+            Sb[q.o0] = q.v0;
+        }
+        if (q.oB >= 0) Sb[q.oB] = q.vB;
       };
       auto score_cell = [&](int i, int ai, uint32_t ms, uint32_t mt, int &off) -> float {
         // the table read is issued by every lane (clamped index), so no branch
@@ -454,7 +471,7 @@ __global__ __launch_bounds__(kSimThreads, 3) void sim_kernel(SimArgs a) {
       // One row at a time (sentences of more than 31 tokens): lane q holds
       // source position q < 64; the mask uses the first word of each entry.
       auto single_row = [&](const int k) {
-        const int i = it.i0 + wv + kSimWaves * k;
+        const int i = row_of(k);
         const int64_t sb = readlane64(rsb, k);
         const int ai = __builtin_amdgcn_readlane(rlen, k);
         const int4 cur = lane < ai ? a.trans[sb + lane] : make_int4(-1, -1, -1, -1);
@@ -608,16 +625,23 @@ __global__ __launch_bounds__(kSimThreads, 3) void sim_kernel(SimArgs a) {
           }
         }
         wave_sync();
-        const int i = it.i0 + wv + kSimWaves * k;
+        const int i = row_of(k);
         int off0, off1 = -1;
         const float sv0 = score_cell(i, ai0, __popc(acc0 & ~kHitBit), mt0, off0);
         float sv1 = 0.0f;
-        if (has1) sv1 = score_cell(i + kSimWaves, ai1, __popc(acc1 & ~kHitBit), mt1, off1);
+        if (has1) sv1 = score_cell(i + 1, ai1, __popc(acc1 & ~kHitBit), mt1, off1);
+        const bool pairable = has1 && ((min(64, n - ((i >> 6) << 6)) & 1) == 0);  // strip of even R
+        const float left_v = shift_up_one_lane(sv1);  // lane c: cell (i + 1, c - 1)
+        const int left_o = __shfl_up(off1, 1);
+        const bool paired = pairable && lane >= 1 && off0 >= 0 && left_o >= 0;
+        const bool right_pairs = __shfl_down(paired ? 1 : 0, 1) != 0 && lane < 63;
         flush(pend);  // this call site's scores of two steps ago
         pend.o0 = off0;
         pend.v0 = sv0;
-        pend.o1 = off1;
-        pend.v1 = sv1;
+        pend.vl = left_v;
+        pend.paired = paired;
+        pend.oB = (off1 >= 0 && !right_pairs) ? off1 : -1;
+        pend.vB = sv1;
       };
       int4 bufA = fetch2(0), bufB;
       Pend qa, qb;
@@ -1030,10 +1054,6 @@ __global__ __launch_bounds__(256) void relayout_kernel(const PairDesc *descs, in
 // back from (n, m), writing the D cells backwards into the pair's output
 // slots; the wave reads their scores, keeps those >= tau and compacts them in
 // path order to the front of the slots.
-__device__ __forceinline__ float shift_up_one_lane(float v) {
-  // wave_shr:1 -- lane l receives lane l-1's value (lane 0 keeps its own)
-  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x138, 0xF, 0xF, false));
-}
 
 constexpr int kNwUnroll = 16;
 // Word 3 of a raw buffer resource on gfx9-family GPUs (32-bit data format).

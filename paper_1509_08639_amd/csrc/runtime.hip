@@ -116,7 +116,7 @@ static inline bool nw_needs_global_row(int64_t n, int64_t m) { return nw_global_
 size_t pair_bytes(int64_t n, int64_t m) {
   size_t b = sizeof(PairDesc) + 4 /*count*/ + 8 /*moves off*/;
   b += (size_t)((n + kMinItemRows - 1) / kMinItemRows) * sizeof(SimItem);  // bound over item sizes
-  b += (size_t)score_slots(n, m) * 4;
+  b += (size_t)score_block(n, m) * 4;
   if (nw_needs_global_dirs(n, m)) b += (size_t)(n * nw_dir_row_words(m)) * 4;
   b += (size_t)nw_global_row_floats(n, m) * 4;
   if (nw_is_big(n)) b += 4;  // its entry in the list of large pairs
@@ -142,7 +142,7 @@ ym_status Chunk::layout(const int64_t *sdo, const int64_t *tdo, int64_t p0_, int
     const int64_t n = sdo[p + 1] - sdo[p], m = tdo[p + 1] - tdo[p];
     if (n > 0 && m > 0) n_items += (n + item_rows - 1) / item_rows;
     cells += n * m;
-    s_slots += score_slots(n, m);
+    s_slots += score_block(n, m);
     if (nw_needs_global_dirs(n, m)) dir_words += n * nw_dir_row_words(m);
     row_floats += nw_global_row_floats(n, m);
     if (nw_is_big(n)) n_big++;
@@ -222,7 +222,7 @@ void Chunk::fill_host(const int64_t *sdo, const int64_t *tdo, char *host) const 
       }
     moff[p - p0] = mv;
     mv += n + m;
-    s_off += score_slots(n, m);
+    s_off += score_block(n, m);
     rm_off += n * m;
     out_off += std::min(n, m);
   }

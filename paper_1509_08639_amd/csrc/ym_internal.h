@@ -50,6 +50,8 @@ __host__ __device__ constexpr int64_t score_slots(int64_t n, int64_t m) {
   return (n <= 0 || m <= 0) ? 0
                             : ((n - 1) / 64) * (m + 63) * 64 + (m + (n - 64 * ((n - 1) / 64)) - 1) * (n - 64 * ((n - 1) / 64));
 }
+// a pair's block in a chunk, rounded up to 16 bytes (blocks start 16-byte aligned)
+__host__ __device__ constexpr int64_t score_block(int64_t n, int64_t m) { return (score_slots(n, m) + 3) & ~int64_t(3); }
 
 // One document pair of a chunk.
 struct PairDesc {
