@@ -469,46 +469,54 @@ __global__ __launch_bounds__(kSimThreads, 3) void sim_kernel(SimArgs a) {
       };
 
       // One row at a time (sentences of more than 31 tokens): lane q holds
-      // source position q < 64; the mask uses the first word of each entry.
+      // source position q < 64.  A mask entry is one 64-bit word here: bits
+      // 0-62 are positions, bit 63 the hit bit, so one pass covers 63
+      // positions (longer sentences take further passes, position bits only).
       auto single_row = [&](const int k) {
         const int i = row_of(k);
         const int64_t sb = readlane64(rsb, k);
         const int ai = __builtin_amdgcn_readlane(rlen, k);
         const int4 cur = lane < ai ? a.trans[sb + lane] : make_int4(-1, -1, -1, -1);
+        unsigned long long *Mq = reinterpret_cast<unsigned long long *>(Mx);
+        constexpr int kPass = 63;
         uint32_t ms_acc = 0, mt_acc = 0;
-        const int npass = ai <= kPosBits ? 1 : (ai + kPosBits - 1) / kPosBits;
+        const int npass = ai <= kPass ? 1 : (ai + kPass - 1) / kPass;
         for (int c = 0; c < npass; c++) {
-          const int qlo = c == 0 ? 0 : kPosBits * c;
-          const int qhi = c == 0 ? ai : min(ai, kPosBits * c + kPosBits);
+          const int qlo = c == 0 ? 0 : kPass * c;
+          const int qhi = c == 0 ? ai : min(ai, kPass * c + kPass);
           for (int q = qlo + lane; q < qhi; q += 64) {
             const int4 t4 = (c == 0 && q < 64) ? cur : a.trans[sb + q];  // cur holds position `lane`
-            const int rel = q - kPosBits * c;
-            const uint32_t bits = (c == 0 ? kHitBit : 0u) | (rel >= 0 && rel < kPosBits ? (1u << rel) : 0u);
+            const int rel = q - kPass * c;
+            const unsigned long long bits =
+                (c == 0 ? (1ull << 63) : 0ull) | (rel >= 0 && rel < kPass ? (1ull << rel) : 0ull);
             if (t4.x == -2) {
               for (int e = 0; e < t4.z; e++) {
                 const int l = u2_lid(uent, a.lex.vals[t4.y + e]);
-                if (l) atomicOr(&Mx[2 * l], bits);
+                if (l) atomicOr(&Mq[l], bits);
               }
             } else {
               const int4 lid = u2_lid4(uent, t4);
               const int l0 = lid.x, l1 = lid.y, l2 = lid.z, l3 = lid.w;
-              if (l0) atomicOr(&Mx[2 * l0], bits);
-              if (l1) atomicOr(&Mx[2 * l1], bits);
-              if (l2) atomicOr(&Mx[2 * l2], bits);
-              if (l3) atomicOr(&Mx[2 * l3], bits);
+              if (l0) atomicOr(&Mq[l0], bits);
+              if (l1) atomicOr(&Mq[l1], bits);
+              if (l2) atomicOr(&Mq[l2], bits);
+              if (l3) atomicOr(&Mq[l3], bits);
             }
           }
           wave_sync();
-          uint32_t acc = 0, mt = 0;
+          uint32_t acc0 = 0, acc1 = 0, mt = 0;
 #pragma unroll
-          for (int g = 0; g < kRegTok / 4; g++) {
-            if (g < ng) {
-              const uint32_t w0 = *reinterpret_cast<const uint32_t *>(Mb + ad[4 * g]);
-              const uint32_t w1 = *reinterpret_cast<const uint32_t *>(Mb + ad[4 * g + 1]);
-              const uint32_t w2 = *reinterpret_cast<const uint32_t *>(Mb + ad[4 * g + 2]);
-              const uint32_t w3 = *reinterpret_cast<const uint32_t *>(Mb + ad[4 * g + 3]);
-              mt += ((w0 >> 31) + (w1 >> 31)) + ((w2 >> 31) + (w3 >> 31));
-              acc |= (w0 | w1) | (w2 | w3);
+          for (int g = 0; g < kRegTok / 8; g++) {
+            if (2 * g < ng) {
+              uint2 w[8];
+#pragma unroll
+              for (int u = 0; u < 8; u++) w[u] = *reinterpret_cast<const uint2 *>(Mb + ad[8 * g + u]);
+#pragma unroll
+              for (int u = 0; u < 8; u += 4) {
+                mt += ((w[u].y >> 31) + (w[u + 1].y >> 31)) + ((w[u + 2].y >> 31) + (w[u + 3].y >> 31));
+                acc0 |= (w[u].x | w[u + 1].x) | (w[u + 2].x | w[u + 3].x);
+                acc1 |= (w[u].y | w[u + 1].y) | (w[u + 2].y | w[u + 3].y);
+              }
             }
           }
           // sentences beyond 32 tokens: the rest straight from LDS, four ids per
@@ -516,13 +524,16 @@ __global__ __launch_bounds__(kSimThreads, 3) void sim_kernel(SimArgs a) {
           for (int k2 = kRegTok; k2 < maxb; k2 += 4) {
             if (k2 < bl) {
               const uint2 ids = *reinterpret_cast<const uint2 *>(tp + k2);
-              const uint32_t w0 = Mx[2 * (ids.x & 0xFFFFu)], w1 = Mx[2 * (ids.x >> 16)];
-              const uint32_t w2 = Mx[2 * (ids.y & 0xFFFFu)], w3 = Mx[2 * (ids.y >> 16)];
-              mt += ((w0 >> 31) + (w1 >> 31)) + ((w2 >> 31) + (w3 >> 31));
-              acc |= (w0 | w1) | (w2 | w3);
+              const uint2 w0 = *reinterpret_cast<const uint2 *>(Mx + 2 * (ids.x & 0xFFFFu));
+              const uint2 w1 = *reinterpret_cast<const uint2 *>(Mx + 2 * (ids.x >> 16));
+              const uint2 w2 = *reinterpret_cast<const uint2 *>(Mx + 2 * (ids.y & 0xFFFFu));
+              const uint2 w3 = *reinterpret_cast<const uint2 *>(Mx + 2 * (ids.y >> 16));
+              mt += ((w0.y >> 31) + (w1.y >> 31)) + ((w2.y >> 31) + (w3.y >> 31));
+              acc0 |= (w0.x | w1.x) | (w2.x | w3.x);
+              acc1 |= (w0.y | w1.y) | (w2.y | w3.y);
             }
           }
-          ms_acc += __popc(acc & ~kHitBit);
+          ms_acc += __popc(acc0) + __popc(acc1 & ~kHitBit);
           if (c == 0) mt_acc = mt;
           wave_sync();
           for (int k2 = lane; k2 < nq4; k2 += 64) reinterpret_cast<uint4 *>(Mx)[k2] = make_uint4(0, 0, 0, 0);

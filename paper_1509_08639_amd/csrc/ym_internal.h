@@ -8,7 +8,7 @@ namespace ym {
 
 constexpr int32_t kEmpty = -1;          // empty hash slot key (lexicon ids are >= 0)
 constexpr uint32_t kHitBit = 0x80000000u;  // "target id is in X_i" flag of a mask word
-constexpr int kPosBits = 31;            // source positions per mask pass
+constexpr int kPosBits = 31;            // source positions per two-row step (bit 31: hit bit)
 
 // Similarity kernel tiling.
 constexpr int kSimThreads = 256;        // 4 waves; each wave owns one source sentence at a time

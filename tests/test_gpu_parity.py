@@ -65,12 +65,19 @@ def test_similarity_single_pair(ym, ctx, O):
 @pytest.mark.parametrize("seed", [1, 2, 3])
 def test_similarity_ragged_edges(ym, ctx, O, seed):
     # empty documents and sentences, negative / unknown ids, source sentences
-    # of more than 31 and 62 tokens (extra mask passes), > 128 source
+    # of more than 31 and 63 tokens (one-row path, extra mask passes), > 128 source
     # sentences (several work items), > 256 target sentences (several chunks)
     lex = parity.random_lexicon(seed)
     c = parity.random_corpus(seed, n_pairs=12, nmax=150, mmax=300, lmax_src=70, lmax_tgt=40)
     w = np.array([-2.0, 3.0, 2.5, 0.75], np.float32)
     _similarity_check(ym, ctx, O, lex, c, w)
+
+
+def test_similarity_long_source_sentences(ym, ctx, O):
+    # source sentences of up to 200 tokens: up to four mask passes of 63 positions
+    lex = parity.random_lexicon(4, vocab=300)
+    c = parity.random_corpus(4, n_pairs=6, nmax=70, mmax=90, lmax_src=200, lmax_tgt=50, vocab=300)
+    _similarity_check(ym, ctx, O, lex, c, np.array([-2.0, 3.0, 2.5, 0.75], np.float32))
 
 
 def test_similarity_chunk_boundaries(ym, ctx, O):
