@@ -233,14 +233,24 @@ __device__ __forceinline__ int64_t score_pos(int i, int c, int n, int m) {
 // every lane walks its sentence's words:
 //   m_t = number of tokens whose word has the top bit,
 //   m_s = popcount of the OR of the words' position bits.
-// Source sentences longer than 31 tokens take one extra pass per further 31
-// positions (position bits only).
+// Two source sentences of at most 31 tokens share a step (one 32-bit word
+// each in an 8-byte entry); a longer one takes a step of its own with the
+// entry as one 64-bit word (63 positions per pass; further passes for longer
+// sentences carry position bits only).
 constexpr int kRegTok = 32;  // target ids per lane held as register addresses
 
 __device__ __forceinline__ int wave_max(int v) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o));
   return v;
+}
+
+// 8-byte LDS read at a 32-bit LDS byte address (the addresses held in
+// registers already include the array's base, so no add per read)
+typedef __attribute__((address_space(3))) const unsigned long long lds_cu64;
+__device__ __forceinline__ uint2 lds_u2_at(uint32_t addr) {
+  const unsigned long long v = *(lds_cu64 *)(uintptr_t)addr;
+  return make_uint2((uint32_t)v, (uint32_t)(v >> 32));
 }
 
 // LDS hash entry of the lanes kernel: key and its dense local id side by
@@ -321,7 +331,7 @@ __global__ __launch_bounds__(kSimThreads, 3) void sim_kernel(SimArgs a) {
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
   uint32_t *Mx = reinterpret_cast<uint32_t *>(Mw2[wv]);
-  const char *Mb = reinterpret_cast<const char *>(&Mw2[0][0]);
+  const uint32_t mw_lds = (uint32_t)(uintptr_t)&Mw2[0][0];  // LDS byte address of the masks
 
   for (int64_t item = blockIdx.x; item < a.n_items; item += gridDim.x) {
     const SimItem it = a.items[item];
@@ -414,15 +424,18 @@ __global__ __launch_bounds__(kSimThreads, 3) void sim_kernel(SimArgs a) {
       }
       __syncthreads();
 
-      // this lane's target sentence and the LDS byte offsets of its mask
-      // entries (from the block's first entry; 8 bytes per local id)
+      // this lane's target sentence and the LDS byte addresses of its mask
+      // entries in this wave's array (8 bytes per local id)
       const bool jok = lane < nj;
       const int bl = jok ? tlen[lane] : 0;
       const uint16_t *tp = tdoc + (jok ? toff[lane] : 0);
-      const uint32_t wbase = (uint32_t)wv * (kTcap + 4) * 8u;
+      const uint32_t wbase = mw_lds + (uint32_t)wv * (kTcap + 4) * 8u;
       uint32_t ad[kRegTok];
 #pragma unroll
-      for (int k = 0; k < kRegTok; k++) ad[k] = wbase + (k < bl ? (uint32_t)tp[k] * 8u : 0u);
+      for (int k = 0; k < kRegTok; k++) {
+        ad[k] = wbase + (k < bl ? (uint32_t)tp[k] * 8u : 0u);
+        asm volatile("" : "+v"(ad[k]));  // keep the whole address in the register (no add per read)
+      }
       const int maxb = __builtin_amdgcn_readfirstlane(wave_max(bl));
       const int ng = (min(maxb, kRegTok) + 3) >> 2;
       const int nq4 = (nlid + 1) >> 1;  // 16-byte stores covering the chunk's entries
@@ -510,7 +523,7 @@ __global__ __launch_bounds__(kSimThreads, 3) void sim_kernel(SimArgs a) {
             if (2 * g < ng) {
               uint2 w[8];
 #pragma unroll
-              for (int u = 0; u < 8; u++) w[u] = *reinterpret_cast<const uint2 *>(Mb + ad[8 * g + u]);
+              for (int u = 0; u < 8; u++) w[u] = lds_u2_at(ad[8 * g + u]);
 #pragma unroll
               for (int u = 0; u < 8; u += 4) {
                 mt += ((w[u].y >> 31) + (w[u + 1].y >> 31)) + ((w[u + 2].y >> 31) + (w[u + 3].y >> 31));
@@ -598,7 +611,7 @@ __global__ __launch_bounds__(kSimThreads, 3) void sim_kernel(SimArgs a) {
           if (2 * g < ng) {
             uint2 w[8];
 #pragma unroll
-            for (int u = 0; u < 8; u++) w[u] = *reinterpret_cast<const uint2 *>(Mb + ad[8 * g + u]);
+            for (int u = 0; u < 8; u++) w[u] = lds_u2_at(ad[8 * g + u]);
 #pragma unroll
             for (int u = 0; u < 8; u += 4) {
               mt0 += ((w[u].x >> 31) + (w[u + 1].x >> 31)) + ((w[u + 2].x >> 31) + (w[u + 3].x >> 31));
