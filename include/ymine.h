@@ -244,7 +244,9 @@ ym_status ym_mine_bidirectional(ym_ctx *ctx, const ym_lexicon *lex_fwd, const ym
  * before starting a server on the context).  None of these choices changes a
  * result: they only change how work is split over workgroups. */
 typedef struct {
-  int32_t sim_kernel;         /* similarity kernel: 1 one lane per target sentence (default), 0 bit-sliced tiles */
+  int32_t sim_kernel;         /* similarity kernel: 1 one lane per target sentence (default); 2 the same,
+                                 with the reads of target sentences longer than 32 tokens split over the
+                                 lanes a chunk leaves spare; 0 bit-sliced tiles */
   int32_t item_rows;          /* source sentences per similarity work item: 64, 128 (default) or 256 */
   int32_t nw_pairs_per_group; /* document pairs per NW workgroup, one wave each: 1 (default), 2 or 4 */
 } ym_tuning;
@@ -255,7 +257,7 @@ ym_status ym_get_tuning(ym_ctx *ctx, ym_tuning *tuning);
 
 /* Autotuner: times the whole path (similarity, NW, compaction) on `sample`
  * with HIP events on the context's stream, `reps` timed passes per candidate
- * after one untimed pass, first over the six (sim_kernel, item_rows) pairs and
+ * after one untimed pass, first over the nine (sim_kernel, item_rows) pairs and
  * then over the NW workgroup sizes with the best of them.  The fastest
  * configuration is applied to the context and returned in *best, its mean
  * time per pass in *best_ms (may be NULL).  On error the previous

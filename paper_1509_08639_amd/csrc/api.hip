@@ -511,7 +511,7 @@ ym_status ym_mine_bidirectional(ym_ctx *c, const ym_lexicon *Lf, const ym_lexico
 // ------------------------------------------------------------ tuning of launches
 static ym_status check_tuning(const ym_tuning *t) {
   if (!t) return fail(YM_EINVAL, "NULL tuning");
-  if (t->sim_kernel != 0 && t->sim_kernel != 1) return fail(YM_EINVAL, "sim_kernel must be 0 or 1");
+  if (t->sim_kernel < 0 || t->sim_kernel > 2) return fail(YM_EINVAL, "sim_kernel must be 0, 1 or 2");
   if (t->item_rows != 64 && t->item_rows != 128 && t->item_rows != 256)
     return fail(YM_EINVAL, "item_rows must be 64, 128 or 256");
   if (t->nw_pairs_per_group != 1 && t->nw_pairs_per_group != 2 && t->nw_pairs_per_group != 4)
@@ -602,7 +602,7 @@ ym_status ym_autotune(ym_ctx *c, const ym_lexicon *L, const ym_batch *b, const y
   ym_tuning win = before;
   double win_ms = 1e300;
   // similarity kernel and item size first (the NW launch is the same for all of them) ...
-  for (int v = 1; v >= 0 && !s; v--)
+  for (int v = 2; v >= 0 && !s; v--)
     for (int rows : {64, 128, 256}) {
       const ym_tuning t{v, rows, before.nw_pairs_per_group};
       double ms = 0;

@@ -245,6 +245,19 @@ __device__ __forceinline__ int wave_max(int v) {
   return v;
 }
 
+// DPP lane moves: quad_perm [1,0,3,2] (0xB1), [2,3,0,1] (0x4E), mirror
+// inside 8 lanes (0x141), mirror inside 16 lanes (0x140)
+template <int kCtrl>
+__device__ __forceinline__ uint32_t dpp_mov(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, kCtrl, 0xF, 0xF, false);
+}
+
+__device__ __forceinline__ int wave_sum(int v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
 // 8-byte LDS read at a 32-bit LDS byte address (the addresses held in
 // registers already include the array's base, so no add per read)
 typedef __attribute__((address_space(3))) const unsigned long long lds_cu64;
@@ -318,6 +331,10 @@ __device__ __forceinline__ int64_t readlane64(int64_t v, int k) {
 
 static_assert(kMaxItemRows / kSimWaves <= 64, "one lane per row of a wave");
 
+// kHelp: chunks holding target sentences of more than 32 tokens use the lanes
+// they leave over to split the reads (below).  A separate instantiation,
+// because the extra code costs registers in the common short-sentence case.
+template <bool kHelp>
 __global__ __launch_bounds__(kSimThreads, 3) void sim_kernel(SimArgs a) {
   __shared__ int2 uent[kUcap];
   __shared__ __align__(16) uint16_t tdoc[kTdocCap];
@@ -327,6 +344,7 @@ __global__ __launch_bounds__(kSimThreads, 3) void sim_kernel(SimArgs a) {
   __shared__ __align__(16) uint2 Mw2[kSimWaves][kTcap + 4];  // per wave and local id: two mask words
   __shared__ int sh_scan[kSimWaves];
   __shared__ int sh_j1;
+  __shared__ uint8_t sh_own[kSimWaves][64];  // helper layout: sentence read by each lane
 
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
@@ -427,16 +445,128 @@ __global__ __launch_bounds__(kSimThreads, 3) void sim_kernel(SimArgs a) {
       // this lane's target sentence and the LDS byte addresses of its mask
       // entries in this wave's array (8 bytes per local id)
       const bool jok = lane < nj;
-      const int bl = jok ? tlen[lane] : 0;
-      const uint16_t *tp = tdoc + (jok ? toff[lane] : 0);
+      const int bl = jok ? tlen[lane] : 0;  // length of target sentence `lane` (this lane's column)
+      // When a chunk holds sentences of more than 32 tokens, lanes it leaves
+      // over help with the reads: sentence j gets g_j = next_pow2(ceil(b_j /
+      // T)) lanes for the smallest T in 4, 8, ..., 32 with sum_j g_j <= 64 (no
+      // help if there is none).  Every read then comes from registers (none
+      // of the extra id reads of long sentences); the mask reads themselves
+      // are as many as before, so chunks of short sentences gain nothing from
+      // helpers and get none.  Groups are laid out largest first, so each
+      // starts at a multiple of its size; lane L reads one segment of its
+      // group's sentence, the group's counts are combined by an xor butterfly
+      // and lane j takes them from its group's first lane.
+      const int maxb0 = __builtin_amdgcn_readfirstlane(wave_max(bl));
+      int gcnt = jok ? 1 : 0, T = 0;
+      for (int t = 4; kHelp && maxb0 > kRegTok && t <= kRegTok; t += 4) {
+        const int q = (bl + t - 1) / t;
+        const int c = jok ? (q <= 1 ? 1 : 1 << (32 - __clz(q - 1))) : 0;
+        if (wave_sum(c) <= 64) {
+          T = t;
+          gcnt = c;
+          break;
+        }
+      }
+      // worth it only when the reads saved outweigh the combining (in units
+      // of one 8-byte read per lane: register batches of 8 ids, then 5 reads
+      // per 4 ids beyond the first 32)
+      auto rcost = [](int x) { return 8 * ((min(x, kRegTok) + 7) >> 3) + 5 * ((max(0, x - kRegTok) + 3) >> 2); };
+      if (T > 0) {
+        const int mg = __builtin_amdgcn_readfirstlane(wave_max(gcnt));
+        if (rcost(T) + 4 + 2 * (31 - __clz(mg)) >= rcost(maxb0)) T = 0;
+      }
+      if (T == 0) gcnt = jok ? 1 : 0;
+      const bool helped = T > 0;  // wave-uniform
+      int gbase = lane;           // first lane of sentence `lane`'s group
+      int rl = bl, rgs = 1;       // this lane's read length and its group's size
+      const uint16_t *rp = tdoc + (jok ? toff[lane] : 0);
+      int maxgs = 1;
+      if (helped) {
+        int off = 0;
+        gbase = 0;
+        for (int sz = 64; sz >= 1; sz >>= 1) {
+          const uint64_t mk = __ballot(gcnt == sz);
+          if (gcnt == sz) gbase = off + sz * __popcll(mk & ((1ull << lane) - 1));
+          off += sz * __popcll(mk);
+        }
+        sh_own[wv][lane] = 0xFF;
+        wave_sync();
+        for (int e = 0; e < gcnt; e++) sh_own[wv][gbase + e] = (uint8_t)lane;
+        wave_sync();
+        const int js = sh_own[wv][lane];
+        const int jsc = js == 0xFF ? 0 : js;
+        const int gsz = __shfl(gcnt, jsc), gb = __shfl(gbase, jsc);
+        rl = 0;
+        if (js != 0xFF) {
+          rgs = gsz;
+          const int b = tlen[js];
+          const int seg = ((b + rgs - 1) / rgs + 3) & ~3;  // a multiple of 4: 8-byte aligned id reads
+          const int ts = min(b, (lane - gb) * seg);
+          rl = min(b, ts + seg) - ts;
+          rp = tdoc + toff[js] + ts;
+        }
+        maxgs = __builtin_amdgcn_readfirstlane(wave_max(gcnt));
+        wave_sync();
+      }
+      const uint16_t *const tp = rp;
       const uint32_t wbase = mw_lds + (uint32_t)wv * (kTcap + 4) * 8u;
       uint32_t ad[kRegTok];
 #pragma unroll
       for (int k = 0; k < kRegTok; k++) {
-        ad[k] = wbase + (k < bl ? (uint32_t)tp[k] * 8u : 0u);
+        ad[k] = wbase + (k < rl ? (uint32_t)tp[k] * 8u : 0u);
         asm volatile("" : "+v"(ad[k]));  // keep the whole address in the register (no add per read)
       }
-      const int maxb = __builtin_amdgcn_readfirstlane(wave_max(bl));
+      const int maxb = __builtin_amdgcn_readfirstlane(wave_max(rl));
+      const uint32_t grp = (uint32_t)gbase | ((uint32_t)rgs << 8);  // both in one register
+      // Combine a group's partial results (two masks OR-ed, one packed sum
+      // added) with an xor-style butterfly; afterwards every lane of a group
+      // holds the group's totals.
+      auto butterfly = [&](uint32_t &o0, uint32_t &o1, uint32_t &sp) {
+        if (maxgs > 1) {
+          const uint32_t a0 = dpp_mov<0xB1>(o0), a1 = dpp_mov<0xB1>(o1), b = dpp_mov<0xB1>(sp);
+          if ((grp >> 8) > 1u) o0 |= a0, o1 |= a1, sp += b;
+        }
+        if (maxgs > 2) {
+          const uint32_t a0 = dpp_mov<0x4E>(o0), a1 = dpp_mov<0x4E>(o1), b = dpp_mov<0x4E>(sp);
+          if ((grp >> 8) > 2u) o0 |= a0, o1 |= a1, sp += b;
+        }
+        if (maxgs > 4) {
+          const uint32_t a0 = dpp_mov<0x141>(o0), a1 = dpp_mov<0x141>(o1), b = dpp_mov<0x141>(sp);
+          if ((grp >> 8) > 4u) o0 |= a0, o1 |= a1, sp += b;
+        }
+        if (maxgs > 8) {
+          const uint32_t a0 = dpp_mov<0x140>(o0), a1 = dpp_mov<0x140>(o1), b = dpp_mov<0x140>(sp);
+          if ((grp >> 8) > 8u) o0 |= a0, o1 |= a1, sp += b;
+        }
+        for (int dd = 16; dd < maxgs; dd <<= 1) {
+          const uint32_t a0 = __shfl_xor(o0, dd), a1 = __shfl_xor(o1, dd), b = __shfl_xor(sp, dd);
+          if ((uint32_t)dd < (grp >> 8)) o0 |= a0, o1 |= a1, sp += b;
+        }
+      };
+      // two-row step: position masks of both rows (hit bit 31) and hit counts
+      // -> m_s and m_t of both rows at lane = sentence
+      auto counts2 = [&](uint32_t o0, uint32_t o1, uint32_t t0, uint32_t t1, int &ms0, int &ms1, int &mt0, int &mt1) {
+        if (!helped) {
+          ms0 = __popc(o0 & ~kHitBit), ms1 = __popc(o1 & ~kHitBit), mt0 = (int)t0, mt1 = (int)t1;
+          return;
+        }
+        uint32_t sp = t0 | (t1 << 16);  // each count <= kTcap < 2^11
+        butterfly(o0, o1, sp);
+        const uint32_t pk = __popc(o0 & ~kHitBit) | (__popc(o1 & ~kHitBit) << 5) | ((sp & 0x7FFu) << 10) | (((sp >> 16) & 0x7FFu) << 21);
+        const uint32_t g = (uint32_t)__shfl((int)pk, (int)(grp & 0xFFu));
+        ms0 = g & 31u, ms1 = (g >> 5) & 31u, mt0 = (g >> 10) & 0x7FFu, mt1 = g >> 21;
+      };
+      // one-row pass: a 64-bit position mask (hit bit 63) and the hit count
+      auto counts1 = [&](uint32_t o0, uint32_t o1, uint32_t t, int &ms, int &mt) {
+        if (!helped) {
+          ms = __popc(o0) + __popc(o1 & ~kHitBit), mt = (int)t;
+          return;
+        }
+        butterfly(o0, o1, t);
+        const uint32_t pk = (__popc(o0) + __popc(o1 & ~kHitBit)) | (t << 6);
+        const uint32_t g = (uint32_t)__shfl((int)pk, (int)(grp & 0xFFu));
+        ms = g & 63u, mt = g >> 6;
+      };
       const int ng = (min(maxb, kRegTok) + 3) >> 2;
       const int nq4 = (nlid + 1) >> 1;  // 16-byte stores covering the chunk's entries
 
@@ -535,7 +665,7 @@ __global__ __launch_bounds__(kSimThreads, 3) void sim_kernel(SimArgs a) {
           // sentences beyond 32 tokens: the rest straight from LDS, four ids per
           // read (sentences are padded to a multiple of 4 with id 0)
           for (int k2 = kRegTok; k2 < maxb; k2 += 4) {
-            if (k2 < bl) {
+            if (k2 < bl) {  // only chunks without helpers get here (rl == bl)
               const uint2 ids = *reinterpret_cast<const uint2 *>(tp + k2);
               const uint2 w0 = *reinterpret_cast<const uint2 *>(Mx + 2 * (ids.x & 0xFFFFu));
               const uint2 w1 = *reinterpret_cast<const uint2 *>(Mx + 2 * (ids.x >> 16));
@@ -546,8 +676,10 @@ __global__ __launch_bounds__(kSimThreads, 3) void sim_kernel(SimArgs a) {
               acc1 |= (w0.y | w1.y) | (w2.y | w3.y);
             }
           }
-          ms_acc += __popc(acc0) + __popc(acc1 & ~kHitBit);
-          if (c == 0) mt_acc = mt;
+          int msp, mtp;
+          counts1(acc0, acc1, mt, msp, mtp);
+          ms_acc += msp;
+          if (c == 0) mt_acc = mtp;
           wave_sync();
           for (int k2 = lane; k2 < nq4; k2 += 64) reinterpret_cast<uint4 *>(Mx)[k2] = make_uint4(0, 0, 0, 0);
           wave_sync();
@@ -622,7 +754,7 @@ __global__ __launch_bounds__(kSimThreads, 3) void sim_kernel(SimArgs a) {
           }
         }
         for (int k2 = kRegTok; k2 < maxb; k2 += 4) {  // beyond 32 tokens, four ids per read
-          if (k2 < bl) {
+          if (k2 < bl) {  // only chunks without helpers get here (rl == bl)
             const uint2 ids = *reinterpret_cast<const uint2 *>(tp + k2);
             const uint2 w0 = *reinterpret_cast<const uint2 *>(Mx + 2 * (ids.x & 0xFFFFu));
             const uint2 w1 = *reinterpret_cast<const uint2 *>(Mx + 2 * (ids.x >> 16));
@@ -634,6 +766,8 @@ __global__ __launch_bounds__(kSimThreads, 3) void sim_kernel(SimArgs a) {
             acc1 |= (w0.y | w1.y) | (w2.y | w3.y);
           }
         }
+        int ms0, ms1, mc0, mc1;
+        counts2(acc0, acc1, mt0, mt1, ms0, ms1, mc0, mc1);
         wave_sync();
         if (mine) {
           if (far) {
@@ -651,9 +785,9 @@ __global__ __launch_bounds__(kSimThreads, 3) void sim_kernel(SimArgs a) {
         wave_sync();
         const int i = row_of(k);
         int off0, off1 = -1;
-        const float sv0 = score_cell(i, ai0, __popc(acc0 & ~kHitBit), mt0, off0);
+        const float sv0 = score_cell(i, ai0, ms0, mc0, off0);
         float sv1 = 0.0f;
-        if (has1) sv1 = score_cell(i + 1, ai1, __popc(acc1 & ~kHitBit), mt1, off1);
+        if (has1) sv1 = score_cell(i + 1, ai1, ms1, mc1, off1);
         const bool pairable = has1 && ((min(64, n - ((i >> 6) << 6)) & 1) == 0);  // strip of even R
         const float left_v = shift_up_one_lane(sv1);  // lane c: cell (i + 1, c - 1)
         const int left_o = __shfl_up(off1, 1);
@@ -1718,8 +1852,10 @@ hipError_t launch_similarity(const SimArgs &a, int grid, int variant, hipStream_
   if (a.n_items <= 0) return hipSuccess;
   if (variant == 0)
     hipLaunchKernelGGL(sim_tile_kernel, dim3(grid), dim3(kTileThreads), 0, st, a);
+  else if (variant == 2)
+    hipLaunchKernelGGL(sim_kernel<true>, dim3(grid), dim3(kSimThreads), 0, st, a);
   else
-    hipLaunchKernelGGL(sim_kernel, dim3(grid), dim3(kSimThreads), 0, st, a);
+    hipLaunchKernelGGL(sim_kernel<false>, dim3(grid), dim3(kSimThreads), 0, st, a);
   return hipGetLastError();
 }
 

@@ -272,7 +272,7 @@ ym_status ym_create(int device, size_t hbm_budget_bytes, ym_ctx **out) {
   c->device = device;
   {
     const char *v = getenv("YM_SIM_KERNEL");
-    c->sim_variant = (v && std::strcmp(v, "tile") == 0) ? 0 : 1;
+    c->sim_variant = !v ? 1 : std::strcmp(v, "tile") == 0 ? 0 : std::strcmp(v, "split") == 0 ? 2 : 1;
   }
   if ((e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking)) != hipSuccess) {
     delete c;

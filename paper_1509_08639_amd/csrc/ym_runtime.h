@@ -97,7 +97,8 @@ struct ym_ctx {
   float table_w[4] = {0, 0, 0, 0};
   bool table_valid = false;
   // launch configuration (ym_set_tuning / ym_autotune; read when work is enqueued)
-  int sim_variant = 1;  // similarity kernel: 1 lane per target sentence (default), 0 bit-sliced tiles (YM_SIM_KERNEL=tile)
+  int sim_variant = 1;  // similarity kernel: 1 lane per target sentence (default), 2 the same with reads of long
+                        // sentences split over spare lanes (YM_SIM_KERNEL=split), 0 bit-sliced tiles (=tile)
   int item_rows = ym::kItemRows;  // source sentences per similarity work item
   int nw_pairs_per_group = 1;     // NW workgroup size in pairs (one wave each)
   // kernel timing

@@ -32,6 +32,15 @@ def ctx(ym):
 
 
 @pytest.fixture(scope="module")
+def ctx_split(ym):
+    """A context whose similarity kernel splits the reads of target sentences
+    longer than 32 tokens over spare lanes (kernel 2)."""
+    c = ym.Context(0)
+    ym.set_tuning(c, 2, 128, 1)
+    return c
+
+
+@pytest.fixture(scope="module")
 def O():
     return oracle.default()
 
@@ -62,25 +71,29 @@ def test_similarity_single_pair(ym, ctx, O):
     _similarity_check(ym, ctx, O, lex, c, synth.weights(cfg.seed))
 
 
-@pytest.mark.parametrize("seed", [1, 2, 3])
-def test_similarity_ragged_edges(ym, ctx, O, seed):
+@pytest.mark.parametrize("seed,split", [(1, False), (2, False), (3, False), (1, True), (2, True)])
+def test_similarity_ragged_edges(ym, ctx, ctx_split, O, seed, split):
     # empty documents and sentences, negative / unknown ids, source sentences
     # of more than 31 and 63 tokens (one-row path, extra mask passes), > 128 source
     # sentences (several work items), > 256 target sentences (several chunks)
     lex = parity.random_lexicon(seed)
     c = parity.random_corpus(seed, n_pairs=12, nmax=150, mmax=300, lmax_src=70, lmax_tgt=40)
     w = np.array([-2.0, 3.0, 2.5, 0.75], np.float32)
-    _similarity_check(ym, ctx, O, lex, c, w)
+    _similarity_check(ym, ctx_split if split else ctx, O, lex, c, w)
 
 
-def test_similarity_long_source_sentences(ym, ctx, O):
-    # source sentences of up to 200 tokens: up to four mask passes of 63 positions
+@pytest.mark.parametrize("split", [False, True])
+def test_similarity_long_sentences(ym, ctx, ctx_split, O, split):
+    # source sentences of up to 200 tokens (up to four mask passes of 63
+    # positions), target sentences of up to 130 (split reads: groups of up to
+    # 8 lanes per sentence)
     lex = parity.random_lexicon(4, vocab=300)
-    c = parity.random_corpus(4, n_pairs=6, nmax=70, mmax=90, lmax_src=200, lmax_tgt=50, vocab=300)
-    _similarity_check(ym, ctx, O, lex, c, np.array([-2.0, 3.0, 2.5, 0.75], np.float32))
+    c = parity.random_corpus(4, n_pairs=8, nmax=70, mmax=90, lmax_src=200, lmax_tgt=130, vocab=300)
+    _similarity_check(ym, ctx_split if split else ctx, O, lex, c, np.array([-2.0, 3.0, 2.5, 0.75], np.float32))
 
 
-def test_similarity_chunk_boundaries(ym, ctx, O):
+@pytest.mark.parametrize("split", [False, True])
+def test_similarity_chunk_boundaries(ym, ctx, ctx_split, O, split):
     # target sentences near the 1024-token chunk limit and many short ones
     lex = parity.random_lexicon(9, vocab=400)
     r = np.random.default_rng(9)
@@ -89,7 +102,8 @@ def test_similarity_chunk_boundaries(ym, ctx, O):
     srcs.append([r.integers(0, 400, 5).astype(np.int32) for _ in range(3)])
     tgts.append([r.integers(0, 400, 3).astype(np.int32) for _ in range(700)])
     c = synth.from_lists(srcs, tgts)
-    _similarity_check(ym, ctx, O, lex, c, np.array([-1.0, 2.0, 2.0, 0.5], np.float32))
+    # one-sentence chunks of 1,024 tokens: with split reads, groups of all 64 lanes
+    _similarity_check(ym, ctx_split if split else ctx, O, lex, c, np.array([-1.0, 2.0, 2.0, 0.5], np.float32))
 
 
 def _nw_cases():
@@ -265,14 +279,15 @@ def test_errors(ym, ctx):
 
 @pytest.mark.parametrize("seed", [5, 6])
 def test_similarity_variants_agree(ym, O, seed):
-    """The bit-sliced tile kernel and the lane-per-sentence kernel give the
-    same counts and scores (both also match the oracle above)."""
+    """The bit-sliced tile kernel and the lane-per-sentence kernel, with and
+    without split reads, give the same counts and scores (all also match the
+    oracle above)."""
     import os
     lex = parity.random_lexicon(seed, vocab=90)
     c = parity.random_corpus(seed, n_pairs=10, nmax=140, mmax=150, lmax_src=70, lmax_tgt=66)
     w = np.array([-2.0, 3.0, 2.5, 0.75], np.float32)
     outs = []
-    for variant in ("tile", "lanes"):
+    for variant in ("tile", "lanes", "split"):
         old = os.environ.get("YM_SIM_KERNEL")
         os.environ["YM_SIM_KERNEL"] = variant
         try:
@@ -286,14 +301,18 @@ def test_similarity_variants_agree(ym, O, seed):
         outs.append(ym.similarity(cx, L, c, w))
         L.close()
         cx.close()
-    for a, b in zip(*outs):
-        assert np.array_equal(a, b)
+    for other in outs[1:]:
+        for a, b in zip(outs[0], other):
+            assert np.array_equal(a, b)
 
 
-def test_scale_workload_sample(ym, ctx, O):
+@pytest.mark.parametrize("split", [False, True])
+def test_scale_workload_sample(ym, ctx, ctx_split, O, split):
     """Pairs of the 1M-pair scale workload (3-60 token sentences, Zipf 1.05,
     1-4 translations per key): rows longer than 31 tokens take the one-row
-    path; the mined sets match the oracle."""
+    path, target sentences longer than 32 tokens the split reads (kernel 2);
+    the mined sets match the oracle."""
+    ctx = ctx_split if split else ctx
     cfg = synth.CONFIGS[4]
     lex = synth.make_lexicon(cfg)
     c = synth.generate(cfg, lex, pair_ids=np.arange(0, 1000000, 20000))

@@ -14,7 +14,7 @@ from . import parity
 pytestmark = pytest.mark.gpu
 
 F32 = np.float32
-CONFIGS = list(itertools.product([1, 0], [64, 128, 256], [1, 2, 4]))
+CONFIGS = list(itertools.product([1, 2, 0], [64, 128, 256], [1, 2, 4]))
 
 
 @pytest.fixture(scope="module")
@@ -34,8 +34,9 @@ def _same(a, b):
 def test_every_configuration_gives_the_same_result(ym):
     ctx = ym.Context(0)
     lex = parity.random_lexicon(21)
-    # more than 256 source sentences in some pairs: several items per pair for every item size
-    c = parity.random_corpus(21, n_pairs=24, nmax=300, mmax=150, lmax_src=40, lmax_tgt=35)
+    # more than 256 source sentences in some pairs: several items per pair for every item size;
+    # target sentences of more than 32 tokens (split reads in kernel 2)
+    c = parity.random_corpus(21, n_pairs=24, nmax=300, mmax=150, lmax_src=40, lmax_tgt=45)
     w = np.array([-1.5, 3.0, 2.0, 0.5], np.float32)
     L = ctx.lexicon(lex.src_ids, lex.off, lex.tgt_ids)
     assert ym.get_tuning(ctx) == dict(sim_kernel=1, item_rows=128, nw_pairs_per_group=1)
@@ -54,7 +55,7 @@ def test_every_configuration_gives_the_same_result(ym):
 
 def test_set_tuning_rejects_other_values(ym):
     ctx = ym.Context(0)
-    for bad in [(2, 128, 1), (1, 96, 1), (1, 512, 1), (1, 128, 3), (0, 128, 8)]:
+    for bad in [(3, 128, 1), (-1, 128, 1), (1, 96, 1), (1, 512, 1), (1, 128, 3), (0, 128, 8)]:
         with pytest.raises(ym.YmError):
             ym.set_tuning(ctx, *bad)
     assert ym.get_tuning(ctx) == dict(sim_kernel=1, item_rows=128, nw_pairs_per_group=1)
