@@ -148,11 +148,20 @@ ym_status Chunk::layout(const int64_t *sdo, const int64_t *tdo, int64_t p0_, int
     if (nw_is_big(n)) n_big++;
     slots += std::min(n, m);
   }
+  // the plan (descriptors, items, move offsets, large-pair list, order) comes
+  // first, laid out as in the pinned staging buffer, so one copy uploads it
   size_t o = 0;
   off_descs = o;
   o = align256(o + (size_t)np * sizeof(PairDesc));
   off_items = o;
   o = align256(o + (size_t)std::max<int64_t>(n_items, 1) * sizeof(SimItem));
+  off_moves_off = o;
+  o = align256(o + (size_t)np * 8);
+  off_big = o;
+  o = align256(o + (size_t)std::max<int64_t>(n_big, 1) * 4);
+  off_order = o;
+  o = align256(o + (size_t)std::max<int64_t>(np, 1) * 4);
+  host_bytes = o;
   off_S = o;
   o = align256(o + (size_t)s_slots * 4);
   off_dirs = o;
@@ -167,27 +176,17 @@ ym_status Chunk::layout(const int64_t *sdo, const int64_t *tdo, int64_t p0_, int
   o = align256(o + (size_t)slots * 4);
   off_counts = o;
   o = align256(o + (size_t)np * 4);
-  off_moves_off = o;
-  o = align256(o + (size_t)np * 8);
-  off_big = o;
-  o = align256(o + (size_t)std::max<int64_t>(n_big, 1) * 4);
-  off_order = o;
-  o = align256(o + (size_t)std::max<int64_t>(np, 1) * 4);
   bytes = o;
-  host_bytes = align256((size_t)np * sizeof(PairDesc)) + align256((size_t)std::max<int64_t>(n_items, 1) * sizeof(SimItem)) +
-               align256((size_t)np * 8) + align256((size_t)std::max<int64_t>(n_big, 1) * 4) +
-               align256((size_t)std::max<int64_t>(np, 1) * 4);
   return YM_OK;
 }
 
 // Fill descriptors / items / move offsets into pinned host memory.
 void Chunk::fill_host(const int64_t *sdo, const int64_t *tdo, char *host) const {
-  PairDesc *descs = (PairDesc *)host;
-  SimItem *items = (SimItem *)(host + align256((size_t)np * sizeof(PairDesc)));
-  int64_t *moff = (int64_t *)(host + align256((size_t)np * sizeof(PairDesc)) +
-                              align256((size_t)std::max<int64_t>(n_items, 1) * sizeof(SimItem)));
-  int32_t *big = (int32_t *)((char *)moff + align256((size_t)np * 8));
-  int32_t *order = (int32_t *)((char *)big + align256((size_t)std::max<int64_t>(n_big, 1) * 4));
+  PairDesc *descs = (PairDesc *)(host + off_descs);
+  SimItem *items = (SimItem *)(host + off_items);
+  int64_t *moff = (int64_t *)(host + off_moves_off);
+  int32_t *big = (int32_t *)(host + off_big);
+  int32_t *order = (int32_t *)(host + off_order);
   int64_t s_off = 0, rm_off = 0, out_off = 0, dir_off = 0, row_off = 0, mv = 0, it = 0, nb = 0;
   for (int64_t p = p0; p < p1; p++) {
     const int64_t n = sdo[p + 1] - sdo[p], m = tdo[p + 1] - tdo[p];
@@ -550,19 +549,9 @@ ym_status run_chunk(ym_ctx *c, const ym_lexicon *L, const DevBatch &b, const ym_
   ym_status s = stg->buf.reserve(ch.host_bytes);
   if (s) return s;
   ch.fill_host(sdo, tdo, (char *)stg->buf.ptr);
-  const size_t dsz = align256((size_t)ch.np * sizeof(PairDesc));
-  const size_t isz = align256((size_t)std::max<int64_t>(ch.n_items, 1) * sizeof(SimItem));
-  const char *hp = (const char *)stg->buf.ptr;
+  // the whole plan in one copy (same layout on both sides)
   // When the work is captured into a graph the caller records stg->done after launching it.
-  if ((e = hipMemcpyAsync(ws + ch.off_descs, hp, dsz, hipMemcpyHostToDevice, st)) != hipSuccess ||
-      (e = hipMemcpyAsync(ws + ch.off_items, hp + dsz, isz, hipMemcpyHostToDevice, st)) != hipSuccess ||
-      (e = hipMemcpyAsync(ws + ch.off_moves_off, hp + dsz + isz, align256((size_t)ch.np * 8), hipMemcpyHostToDevice, st)) !=
-          hipSuccess ||
-      (ch.n_big > 0 && (e = hipMemcpyAsync(ws + ch.off_big, hp + dsz + isz + align256((size_t)ch.np * 8),
-                                           (size_t)ch.n_big * 4, hipMemcpyHostToDevice, st)) != hipSuccess) ||
-      (e = hipMemcpyAsync(ws + ch.off_order,
-                          hp + dsz + isz + align256((size_t)ch.np * 8) + align256((size_t)std::max<int64_t>(ch.n_big, 1) * 4),
-                          (size_t)ch.np * 4, hipMemcpyHostToDevice, st)) != hipSuccess ||
+  if ((e = hipMemcpyAsync(ws + ch.off_descs, stg->buf.ptr, ch.host_bytes, hipMemcpyHostToDevice, st)) != hipSuccess ||
       (!stg->caller_syncs && (e = hipEventRecord(stg->done, st)) != hipSuccess))
     return hip_fail(e, "plan upload");
 
