@@ -220,6 +220,20 @@ __device__ __forceinline__ int64_t score_pos(int i, int c, int n, int m) {
   return (int64_t)s * (m + 63) * 64 + (int64_t)(l + c) * R + l;
 }
 
+// End of the target chunk starting at sentence j0, by the first wave: the
+// largest j1 <= j0 + 64 whose sentences [j0, j1) hold at most kTcap tokens
+// (at least one sentence).  Lane L tests j1 = j0 + 1 + L, all in one round of
+// loads; the chunk ends before the first candidate that does not fit.
+__device__ __forceinline__ void chunk_end(const int64_t *toffs, int j0, int m, int64_t n_tok, int *out) {
+  const int lane = threadIdx.x & 63;
+  const int64_t base = clamp64(toffs[j0], 0, n_tok);
+  const int jj = j0 + 1 + lane;
+  const bool fits = jj <= min(m, j0 + kJcap) && clamp64(toffs[jj], 0, n_tok) - base <= kTcap;
+  const uint64_t bal = __ballot(fits);
+  const int lead = ~bal == 0 ? 64 : __builtin_ctzll(~bal);  // candidates that fit, from the first on
+  if (lane == 0) *out = j0 + max(1, lead);
+}
+
 // ------------------------------------------------------ (a) similarity
 // One work item = (pair, source sentences [i0, i1)).  Target sentences are
 // taken in chunks of at most 64 sentences and kTcap tokens.  Each chunk's
@@ -373,18 +387,7 @@ __global__ __launch_bounds__(kSimThreads, 3) void sim_kernel(SimArgs a) {
     }
 
     for (int j0 = 0; j0 < m;) {
-      if (tid == 0) {
-        const int64_t base = clamp64(toffs[j0], 0, a.n_tgt_tok);
-        int lo = j0 + 1, hi = min(m, j0 + kJcap);
-        while (lo < hi) {  // largest j1 whose tokens [j0, j1) fit kTcap (at least one sentence)
-          const int mid = (lo + hi + 1) >> 1;
-          if (clamp64(toffs[mid], 0, a.n_tgt_tok) - base <= kTcap)
-            lo = mid;
-          else
-            hi = mid - 1;
-        }
-        sh_j1 = lo;
-      }
+      if (tid < 64) chunk_end(toffs, j0, m, a.n_tgt_tok, &sh_j1);
       for (int s = tid; s < kUcap; s += kSimThreads) uent[s] = make_int2(kEmpty, 0);
       __syncthreads();
       const int j1 = sh_j1;
@@ -1084,18 +1087,7 @@ __global__ __launch_bounds__(kTileThreads) void sim_tile_kernel(SimArgs a) {
     const int64_t *soffs = a.src_sent_off + d.src_sent0;
 
     for (int j0 = 0; j0 < m;) {
-      if (tid == 0) {
-        const int64_t base = clamp64(toffs[j0], 0, a.n_tgt_tok);
-        int lo = j0 + 1, hi = min(m, j0 + kJcap);
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (clamp64(toffs[mid], 0, a.n_tgt_tok) - base <= kTcap)
-            lo = mid;
-          else
-            hi = mid - 1;
-        }
-        sh_j1 = lo;
-      }
+      if (tid < 64) chunk_end(toffs, j0, m, a.n_tgt_tok, &sh_j1);
       for (int s = tid; s < kUcap; s += kTileThreads) ukey[s] = kEmpty;
       __syncthreads();
       const int j1 = sh_j1;
