@@ -223,15 +223,19 @@ __device__ __forceinline__ int64_t score_pos(int i, int c, int n, int m) {
 // End of the target chunk starting at sentence j0, by the first wave: the
 // largest j1 <= j0 + 64 whose sentences [j0, j1) hold at most kTcap tokens
 // (at least one sentence).  Lane L tests j1 = j0 + 1 + L, all in one round of
-// loads; the chunk ends before the first candidate that does not fit.
-__device__ __forceinline__ void chunk_end(const int64_t *toffs, int j0, int m, int64_t n_tok, int *out) {
+// loads; the chunk ends before the first candidate that does not fit.  With
+// `ends`, lane L also keeps the end of the chunk's sentence L relative to the
+// chunk's first token (clamped to [0, 2^30]).
+__device__ __forceinline__ void chunk_end(const int64_t *toffs, int j0, int m, int64_t n_tok, int *out, int *ends) {
   const int lane = threadIdx.x & 63;
   const int64_t base = clamp64(toffs[j0], 0, n_tok);
   const int jj = j0 + 1 + lane;
-  const bool fits = jj <= min(m, j0 + kJcap) && clamp64(toffs[jj], 0, n_tok) - base <= kTcap;
-  const uint64_t bal = __ballot(fits);
+  const bool ok = jj <= min(m, j0 + kJcap);
+  const int64_t e = ok ? clamp64(toffs[jj], 0, n_tok) - base : 0;
+  const uint64_t bal = __ballot(ok && e <= kTcap);
   const int lead = ~bal == 0 ? 64 : __builtin_ctzll(~bal);  // candidates that fit, from the first on
   if (lane == 0) *out = j0 + max(1, lead);
+  if (ends) ends[lane] = (int)clamp64(e, 0, 1 << 30);
 }
 
 // ------------------------------------------------------ (a) similarity
@@ -358,6 +362,7 @@ __global__ __launch_bounds__(kSimThreads, 3) void sim_kernel(SimArgs a) {
   __shared__ __align__(16) uint2 Mw2[kSimWaves][kTcap + 4];  // per wave and local id: two mask words
   __shared__ int sh_scan[kSimWaves];
   __shared__ int sh_j1;
+  __shared__ int sh_ends[kJcap];  // chunk's sentence ends, relative to its first token
   __shared__ uint8_t sh_own[kSimWaves][64];  // helper layout: sentence read by each lane
 
   const int tid = threadIdx.x, lane = tid & 63;
@@ -387,18 +392,18 @@ __global__ __launch_bounds__(kSimThreads, 3) void sim_kernel(SimArgs a) {
     }
 
     for (int j0 = 0; j0 < m;) {
-      if (tid < 64) chunk_end(toffs, j0, m, a.n_tgt_tok, &sh_j1);
+      if (tid < 64) chunk_end(toffs, j0, m, a.n_tgt_tok, &sh_j1, sh_ends);
       for (int s = tid; s < kUcap; s += kSimThreads) uent[s] = make_int2(kEmpty, 0);
       __syncthreads();
       const int j1 = sh_j1;
       const int nj = j1 - j0;
       const int64_t tbase = clamp64(toffs[j0], 0, a.n_tgt_tok);
-      const int ntok = (int)clamp64(clamp64(toffs[j1], 0, a.n_tgt_tok) - tbase, 0, kTcap);
+      const int ntok = min(sh_ends[nj - 1], kTcap);
       // sentence jj = tid: original local start, length, and start in the padded staging
       int blen = 0;
       if (tid < nj) {
-        const int ostart = (int)clamp64(clamp64(toffs[j0 + tid], 0, a.n_tgt_tok) - tbase, 0, ntok);
-        const int oend = (int)clamp64(clamp64(toffs[j0 + tid + 1], 0, a.n_tgt_tok) - tbase, ostart, ntok);
+        const int ostart = tid == 0 ? 0 : min(sh_ends[tid - 1], ntok);
+        const int oend = min(max(sh_ends[tid], ostart), ntok);
         blen = oend - ostart;
         toff_o[tid] = (uint16_t)ostart;
         tlen[tid] = (uint16_t)blen;
@@ -1087,7 +1092,7 @@ __global__ __launch_bounds__(kTileThreads) void sim_tile_kernel(SimArgs a) {
     const int64_t *soffs = a.src_sent_off + d.src_sent0;
 
     for (int j0 = 0; j0 < m;) {
-      if (tid < 64) chunk_end(toffs, j0, m, a.n_tgt_tok, &sh_j1);
+      if (tid < 64) chunk_end(toffs, j0, m, a.n_tgt_tok, &sh_j1, nullptr);
       for (int s = tid; s < kUcap; s += kTileThreads) ukey[s] = kEmpty;
       __syncthreads();
       const int j1 = sh_j1;
