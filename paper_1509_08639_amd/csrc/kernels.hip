@@ -399,6 +399,15 @@ __global__ __launch_bounds__(kSimThreads, 3) void sim_kernel(SimArgs a) {
       const int nj = j1 - j0;
       const int64_t tbase = clamp64(toffs[j0], 0, a.n_tgt_tok);
       const int ntok = min(sh_ends[nj - 1], kTcap);
+      // the chunk's tokens, up to kTcap / kSimThreads per thread: all loads in flight at once
+      constexpr int kTpt = kTcap / kSimThreads;
+      static_assert(kTpt * kSimThreads == kTcap, "every staged token has a thread");
+      int32_t xs[kTpt];
+#pragma unroll
+      for (int u = 0; u < kTpt; u++) {
+        const int p = tid + kSimThreads * u;
+        xs[u] = p < ntok ? a.tgt_tok[tbase + p] : -1;
+      }
       // sentence jj = tid: original local start, length, and start in the padded staging
       int blen = 0;
       if (tid < nj) {
@@ -414,17 +423,16 @@ __global__ __launch_bounds__(kSimThreads, 3) void sim_kernel(SimArgs a) {
       if (tid == 0) toff_o[nj] = (uint16_t)ntok;
       for (int q = tid; q < npad; q += kSimThreads) tdoc[q] = 0xFFFF;
       __syncthreads();
-      for (int p = tid; p < ntok; p += kSimThreads) {
-        int lo = 0, hi = nj - 1;  // sentence holding token p: last start <= p
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (toff_o[mid] <= p)
-            lo = mid;
-          else
-            hi = mid - 1;
+#pragma unroll
+      for (int u = 0; u < kTpt; u++) {
+        const int p = tid + kSimThreads * u;
+        if (p < ntok) {
+          int lo = 0;  // sentence holding token p: the last start <= p (starts are non-decreasing)
+#pragma unroll
+          for (int step = kJcap / 2; step >= 1; step >>= 1)
+            if (lo + step < nj && toff_o[lo + step] <= p) lo += step;
+          tdoc[toff[lo] + (p - toff_o[lo])] = xs[u] < 0 ? (uint16_t)0xFFFF : (uint16_t)u2_insert(uent, xs[u]);
         }
-        const int32_t x = a.tgt_tok[tbase + p];
-        tdoc[toff[lo] + (p - toff_o[lo])] = x < 0 ? (uint16_t)0xFFFF : (uint16_t)u2_insert(uent, x);
       }
       __syncthreads();
       // dense local ids 1..nlid-1 in slot order (0 = "no such id", its word stays 0)
