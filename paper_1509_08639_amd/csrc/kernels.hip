@@ -370,6 +370,13 @@ __global__ __launch_bounds__(kSimThreads, 3) void sim_kernel(SimArgs a) {
   uint32_t *Mx = reinterpret_cast<uint32_t *>(Mw2[wv]);
   const uint32_t mw_lds = (uint32_t)(uintptr_t)&Mw2[0][0];  // LDS byte address of the masks
 
+  // The mask words start at zero once; every step clears what it set (the
+  // one-row path clears all the chunk's entries), so they are zero again at
+  // the start of every step and chunk.
+  for (int k = tid; k < kSimWaves * (kTcap + 4) / 2; k += kSimThreads)
+    reinterpret_cast<uint4 *>(&Mw2[0][0])[k] = make_uint4(0, 0, 0, 0);
+  __syncthreads();
+
   for (int64_t item = blockIdx.x; item < a.n_items; item += gridDim.x) {
     const SimItem it = a.items[item];
     const PairDesc d = a.descs[it.pair];
@@ -448,9 +455,6 @@ __global__ __launch_bounds__(kSimThreads, 3) void sim_kernel(SimArgs a) {
         if (uent[s].x != kEmpty) uent[s].y = 1 + r++;
       }
       const int nlid = total + 1;
-      // every wave's mask words start at zero; each source sentence clears what it set
-      for (int k = tid; k < kSimWaves * (kTcap + 4) / 2; k += kSimThreads)
-        reinterpret_cast<uint4 *>(&Mw2[0][0])[k] = make_uint4(0, 0, 0, 0);
       __syncthreads();
       for (int q = tid; q < npad; q += kSimThreads) {
         const uint16_t s = tdoc[q];
