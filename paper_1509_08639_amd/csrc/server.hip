@@ -76,7 +76,9 @@ struct Slot {
   int64_t cap = 0;  // output capacity of the step
   size_t off_out = 0;
   ym_status launch_status = YM_OK;
-  hipGraphExec_t exec = nullptr;  // the last step's executable graph (graph mode)
+  // executable graphs of the last steps (graph mode), one per step shape:
+  // without and with the large-pair NW launch
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
   int64_t graph_updates = 0, graph_instantiations = 0;
 };
 
@@ -206,28 +208,29 @@ ym_status launch_step(ym_server *S, Slot &sl) {
     hipGraph_t g = nullptr;
     if ((e = hipStreamEndCapture(sl.stream, &g)) || !g) return hip_fail(e ? e : hipErrorUnknown, "end capture");
     bool updated = false;
-    if (sl.exec) {
+    hipGraphExec_t &ex = sl.exec[ch.n_big > 0 ? 1 : 0];
+    if (ex) {
       hipGraphNode_t err_node = nullptr;
       hipGraphExecUpdateResult res = hipGraphExecUpdateError;
-      if (hipGraphExecUpdate(sl.exec, g, &err_node, &res) == hipSuccess && res == hipGraphExecUpdateSuccess) {
+      if (hipGraphExecUpdate(ex, g, &err_node, &res) == hipSuccess && res == hipGraphExecUpdateSuccess) {
         updated = true;
         sl.graph_updates++;
       } else {
         (void)hipGetLastError();
-        hipGraphExecDestroy(sl.exec);
-        sl.exec = nullptr;
+        hipGraphExecDestroy(ex);
+        ex = nullptr;
       }
     }
     if (!updated) {
-      if ((e = hipGraphInstantiate(&sl.exec, g, nullptr, nullptr, 0))) {
+      if ((e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0))) {
         hipGraphDestroy(g);
-        sl.exec = nullptr;
+        ex = nullptr;
         return hip_fail(e, "graph instantiate");
       }
       sl.graph_instantiations++;
     }
     hipGraphDestroy(g);
-    if ((e = hipGraphLaunch(sl.exec, sl.stream))) return hip_fail(e, "graph launch");
+    if ((e = hipGraphLaunch(ex, sl.stream))) return hip_fail(e, "graph launch");
     if ((e = hipEventRecord(sl.stage.done, sl.stream))) return hip_fail(e, "staging event");
   }
   if ((e = hipEventRecord(sl.done, sl.stream))) return hip_fail(e, "step event");
@@ -560,7 +563,8 @@ ym_status ym_server_stop(ym_server *S) {
     sl.hin.release();
     sl.hout.release();
     sl.stage.buf.release();
-    if (sl.exec) hipGraphExecDestroy(sl.exec);
+    for (hipGraphExec_t &x : sl.exec)
+      if (x) hipGraphExecDestroy(x);
     hipEventDestroy(sl.done);
     hipEventDestroy(sl.stage.done);
     hipStreamDestroy(sl.stream);
