@@ -325,12 +325,21 @@ ym_status ym_mine_device(ym_ctx *c, const ym_lexicon *L, const ym_device_batch *
     hipError_t e = hipMemsetAsync(out->pair_off, 0, 8, st);
     return e ? hip_fail(e, "memset") : YM_OK;
   }
+  // the first chunk's plan goes up on the upload stream while the tokens are translated
+  char *ws = (char *)workspace + head;
+  Chunk first;
+  first.layout(b->src_doc_off, b->tgt_doc_off, chunks[0].first, chunks[0].second, c->item_rows);
+  if (first.bytes > workspace_bytes - head) return fail(YM_ENOMEM, "workspace too small");
+  if ((s = upload_plan(c, b->src_doc_off, b->tgt_doc_off, first, ws, st, nullptr, true))) return s;
   if ((s = translate_batch(c, L, d, (char *)workspace, st))) return s;
-  for (auto &ck : chunks) {
+  hipError_t e = hipStreamWaitEvent(st, c->ev_up, 0);
+  if (e) return hip_fail(e, "plan upload wait");
+  for (size_t k = 0; k < chunks.size(); k++) {
     Chunk ch;
-    ch.layout(b->src_doc_off, b->tgt_doc_off, ck.first, ck.second, c->item_rows);
-    if (ch.bytes > workspace_bytes - head) return fail(YM_ENOMEM, "workspace too small");
-    if ((s = run_chunk(c, L, d, prm, b->src_doc_off, b->tgt_doc_off, ch, (char *)workspace + head, *out, st, nullptr)))
+    if (k) ch.layout(b->src_doc_off, b->tgt_doc_off, chunks[k].first, chunks[k].second, c->item_rows);
+    const Chunk &cc = k ? ch : first;
+    if (cc.bytes > workspace_bytes - head) return fail(YM_ENOMEM, "workspace too small");
+    if ((s = run_chunk(c, L, d, prm, b->src_doc_off, b->tgt_doc_off, cc, ws, *out, st, nullptr, nullptr, k == 0)))
       return s;
   }
   return YM_OK;

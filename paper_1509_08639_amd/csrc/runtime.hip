@@ -277,10 +277,16 @@ ym_status ym_create(int device, size_t hbm_budget_bytes, ym_ctx **out) {
     delete c;
     return hip_fail(e, "hipStreamCreate");
   }
-  if ((e = hipEventCreateWithFlags(&c->stage.done, hipEventDisableTiming)) != hipSuccess) {
+  if ((e = hipEventCreateWithFlags(&c->stage.done, hipEventDisableTiming)) != hipSuccess ||
+      (e = hipEventCreateWithFlags(&c->ev_ws_free, hipEventDisableTiming)) != hipSuccess ||
+      (e = hipEventCreateWithFlags(&c->ev_up, hipEventDisableTiming)) != hipSuccess ||
+      (e = hipStreamCreateWithFlags(&c->up_stream, hipStreamNonBlocking)) != hipSuccess) {
+    if (c->stage.done) hipEventDestroy(c->stage.done);
+    if (c->ev_ws_free) hipEventDestroy(c->ev_ws_free);
+    if (c->ev_up) hipEventDestroy(c->ev_up);
     hipStreamDestroy(c->stream);
     delete c;
-    return hip_fail(e, "hipEventCreate");
+    return hip_fail(e, "hipEventCreate / hipStreamCreate");
   }
   size_t free_b = 0, total_b = 0;
   if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = total_b = 0;
@@ -294,6 +300,7 @@ void ym_destroy(ym_ctx *c) {
   if (!c) return;
   hipSetDevice(c->device);
   hipStreamSynchronize(c->stream);
+  hipStreamSynchronize(c->up_stream);
   for (auto &t : c->ev_pending) {
     hipEventDestroy(t.a);
     hipEventDestroy(t.b);
@@ -306,6 +313,9 @@ void ym_destroy(ym_ctx *c) {
   c->stage.buf.release();
   c->host_out.release();
   hipEventDestroy(c->stage.done);
+  hipEventDestroy(c->ev_ws_free);
+  hipEventDestroy(c->ev_up);
+  hipStreamDestroy(c->up_stream);
   hipStreamDestroy(c->stream);
   delete c;
 }
@@ -539,9 +549,8 @@ ym_status plan_chunks(const int64_t *sdo, const int64_t *tdo, int64_t n_pairs, s
 }
 
 // Enqueue one chunk: upload its plan, then the four kernels.
-ym_status run_chunk(ym_ctx *c, const ym_lexicon *L, const DevBatch &b, const ym_params *prm, const int64_t *sdo,
-                    const int64_t *tdo, const Chunk &ch, char *ws, const ym_device_out &out, hipStream_t st,
-                    const DebugOut *dbg, Staging *stg) {
+ym_status upload_plan(ym_ctx *c, const int64_t *sdo, const int64_t *tdo, const Chunk &ch, char *ws, hipStream_t st,
+                      Staging *stg, bool side) {
   // plan -> pinned staging -> workspace (wait for the previous upload to have left the staging buffer)
   if (!stg) stg = &c->stage;
   hipError_t e = stg->caller_syncs ? hipSuccess : hipEventSynchronize(stg->done);
@@ -549,11 +558,29 @@ ym_status run_chunk(ym_ctx *c, const ym_lexicon *L, const DevBatch &b, const ym_
   ym_status s = stg->buf.reserve(ch.host_bytes);
   if (s) return s;
   ch.fill_host(sdo, tdo, (char *)stg->buf.ptr);
-  // the whole plan in one copy (same layout on both sides)
-  // When the work is captured into a graph the caller records stg->done after launching it.
-  if ((e = hipMemcpyAsync(ws + ch.off_descs, stg->buf.ptr, ch.host_bytes, hipMemcpyHostToDevice, st)) != hipSuccess ||
-      (!stg->caller_syncs && (e = hipEventRecord(stg->done, st)) != hipSuccess))
+  // the whole plan in one copy (same layout on both sides); on the upload
+  // stream once the work already on `st` (which may read the previous plan)
+  // is done.  When the work is captured into a graph the caller records
+  // stg->done after launching it.
+  hipStream_t us = st;
+  if (side) {
+    if ((e = hipEventRecord(c->ev_ws_free, st)) != hipSuccess || (e = hipStreamWaitEvent(c->up_stream, c->ev_ws_free, 0)))
+      return hip_fail(e, "plan upload order");
+    us = c->up_stream;
+  }
+  if ((e = hipMemcpyAsync(ws + ch.off_descs, stg->buf.ptr, ch.host_bytes, hipMemcpyHostToDevice, us)) != hipSuccess ||
+      (!stg->caller_syncs && (e = hipEventRecord(stg->done, us)) != hipSuccess) ||
+      (side && (e = hipEventRecord(c->ev_up, us)) != hipSuccess))
     return hip_fail(e, "plan upload");
+  return YM_OK;
+}
+
+ym_status run_chunk(ym_ctx *c, const ym_lexicon *L, const DevBatch &b, const ym_params *prm, const int64_t *sdo,
+                    const int64_t *tdo, const Chunk &ch, char *ws, const ym_device_out &out, hipStream_t st,
+                    const DebugOut *dbg, Staging *stg, bool plan_ready) {
+  hipError_t e;
+  ym_status s;
+  if (!plan_ready && (s = upload_plan(c, sdo, tdo, ch, ws, st, stg, false))) return s;
 
   const PairDesc *descs = (const PairDesc *)(ws + ch.off_descs);
   float *S = (float *)(ws + ch.off_S);  // strip-diagonal layout

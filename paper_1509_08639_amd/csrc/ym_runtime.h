@@ -79,15 +79,23 @@ struct Staging {
   bool caller_syncs = false;  // the caller waits for and records `done` (work captured into a graph)
 };
 
+// Upload a chunk's plan (descriptors, items, ...) into the workspace: on `st`,
+// or with `side` on the context's upload stream after the work already on
+// `st`, recording c->ev_up when done (the caller makes `st` wait for it).
+ym_status upload_plan(ym_ctx *c, const int64_t *sdo, const int64_t *tdo, const Chunk &ch, char *ws, hipStream_t st,
+                      Staging *stg, bool side);
+// Enqueue one chunk: its plan upload (unless `plan_ready`), then the kernels.
 ym_status run_chunk(ym_ctx *c, const ym_lexicon *L, const DevBatch &b, const ym_params *prm, const int64_t *sdo,
                     const int64_t *tdo, const Chunk &ch, char *ws, const ym_device_out &out, hipStream_t st,
-                    const DebugOut *dbg, Staging *stg = nullptr);
+                    const DebugOut *dbg, Staging *stg = nullptr, bool plan_ready = false);
 
 }  // namespace ym
 
 struct ym_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
+  hipStream_t up_stream = nullptr;  // plan uploads that overlap the translation kernel
+  hipEvent_t ev_ws_free = nullptr, ev_up = nullptr;
   ym::Staging stage;
   size_t budget = 0;       // serving HBM budget
   size_t arena_limit = 0;  // workspace cap for host-API calls
