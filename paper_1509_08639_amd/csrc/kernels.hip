@@ -285,12 +285,16 @@ __device__ __forceinline__ uint2 lds_u2_at(uint32_t addr) {
 }
 
 // LDS hash entry of the lanes kernel: key and its dense local id side by
-// side, so a lookup is one 8-byte read.
-__device__ __forceinline__ int u2_insert(int2 *ent, int32_t x) {
+// side, so a lookup is one 8-byte read.  Insert target id x (>= 0): its
+// slot, and whether x was new to the table.
+__device__ __forceinline__ int u2_insert_fresh(int2 *ent, int32_t x, bool &fresh) {
   uint32_t h = hash32(x) >> (32 - kLogUcap);
   for (;;) {  // at most kTcap distinct keys in kUcap slots
     const int prev = atomicCAS(&ent[h].x, kEmpty, x);
-    if (prev == kEmpty || prev == x) return (int)h;
+    if (prev == kEmpty || prev == x) {
+      fresh = prev == kEmpty;
+      return (int)h;
+    }
     h = (h + 1) & (kUcap - 1);
   }
 }
@@ -363,6 +367,7 @@ __global__ __launch_bounds__(kSimThreads, 3) void sim_kernel(SimArgs a) {
   __shared__ int sh_scan[kSimWaves];
   __shared__ int sh_j1;
   __shared__ int sh_ends[kJcap];  // chunk's sentence ends, relative to its first token
+  __shared__ int sh_nlid, sh_npad;  // chunk's distinct ids, padded staging length
   __shared__ uint8_t sh_own[kSimWaves][64];  // helper layout: sentence read by each lane
 
   const int tid = threadIdx.x, lane = tid & 63;
@@ -400,6 +405,7 @@ __global__ __launch_bounds__(kSimThreads, 3) void sim_kernel(SimArgs a) {
 
     for (int j0 = 0; j0 < m;) {
       if (tid < 64) chunk_end(toffs, j0, m, a.n_tgt_tok, &sh_j1, sh_ends);
+      if (tid == 0) sh_nlid = 0;
       for (int s = tid; s < kUcap; s += kSimThreads) uent[s] = make_int2(kEmpty, 0);
       __syncthreads();
       const int j1 = sh_j1;
@@ -415,47 +421,62 @@ __global__ __launch_bounds__(kSimThreads, 3) void sim_kernel(SimArgs a) {
         const int p = tid + kSimThreads * u;
         xs[u] = p < ntok ? a.tgt_tok[tbase + p] : -1;
       }
-      // sentence jj = tid: original local start, length, and start in the padded staging
-      int blen = 0;
-      if (tid < nj) {
-        const int ostart = tid == 0 ? 0 : min(sh_ends[tid - 1], ntok);
-        const int oend = min(max(sh_ends[tid], ostart), ntok);
-        blen = oend - ostart;
-        toff_o[tid] = (uint16_t)ostart;
-        tlen[tid] = (uint16_t)blen;
+      // the chunk's sentences, one per lane of the first wave: local start,
+      // length, start in the padded staging (each padded to a multiple of 4
+      // with "no id"), by a wave-wide scan
+      if (tid < 64) {
+        int ostart = 0, blen = 0;
+        if (lane < nj) {
+          ostart = lane == 0 ? 0 : min(sh_ends[lane - 1], ntok);
+          blen = min(max(sh_ends[lane], ostart), ntok) - ostart;
+        }
+        const int plen = (blen + 3) & ~3;
+        int x = plen;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+          const int y = __shfl_up(x, o);
+          if (lane >= o) x += y;
+        }
+        const int pstart = x - plen;
+        if (lane < nj) {
+          toff_o[lane] = (uint16_t)ostart;
+          tlen[lane] = (uint16_t)blen;
+          toff[lane] = (uint16_t)pstart;
+          for (int q = blen; q < plen; q++) tdoc[pstart + q] = 0xFFFF;
+        }
+        if (lane == 0) toff_o[nj] = (uint16_t)ntok;
+        if (lane == 63) sh_npad = x;
       }
-      int npad;
-      const int pstart = block_excl_sum256((blen + 3) & ~3, sh_scan, &npad);
-      if (tid < nj) toff[tid] = (uint16_t)pstart;
-      if (tid == 0) toff_o[nj] = (uint16_t)ntok;
-      for (int q = tid; q < npad; q += kSimThreads) tdoc[q] = 0xFFFF;
       __syncthreads();
+      const int npad = sh_npad;
+      // Each token goes into the hash; a key new to the chunk takes the next
+      // dense local id (1, 2, ...; one LDS atomic per wave and round, 0 = "no
+      // such id", its mask word stays 0).
 #pragma unroll
       for (int u = 0; u < kTpt; u++) {
         const int p = tid + kSimThreads * u;
+        bool fresh = false;
+        int h = 0xFFFF, dst = -1;
         if (p < ntok) {
           int lo = 0;  // sentence holding token p: the last start <= p (starts are non-decreasing)
 #pragma unroll
           for (int step = kJcap / 2; step >= 1; step >>= 1)
             if (lo + step < nj && toff_o[lo + step] <= p) lo += step;
-          tdoc[toff[lo] + (p - toff_o[lo])] = xs[u] < 0 ? (uint16_t)0xFFFF : (uint16_t)u2_insert(uent, xs[u]);
+          dst = toff[lo] + (p - toff_o[lo]);
+          if (xs[u] >= 0) h = u2_insert_fresh(uent, xs[u], fresh);
         }
+        const uint64_t nb = __ballot(fresh);
+        if (nb) {
+          const int lead = __builtin_ctzll(nb);
+          int base = 0;
+          if (lane == lead) base = atomicAdd(&sh_nlid, __popcll(nb));
+          base = __builtin_amdgcn_readlane(base, lead);
+          if (fresh) uent[h].y = 1 + base + __popcll(nb & ((1ull << lane) - 1));
+        }
+        if (dst >= 0) tdoc[dst] = (uint16_t)h;
       }
       __syncthreads();
-      // dense local ids 1..nlid-1 in slot order (0 = "no such id", its word stays 0)
-      constexpr int kSpt = kUcap / kSimThreads;
-      int cnt = 0;
-#pragma unroll
-      for (int k = 0; k < kSpt; k++) cnt += (uent[tid * kSpt + k].x != kEmpty);
-      int total;
-      int r = block_excl_sum256(cnt, sh_scan, &total);
-#pragma unroll
-      for (int k = 0; k < kSpt; k++) {
-        const int s = tid * kSpt + k;
-        if (uent[s].x != kEmpty) uent[s].y = 1 + r++;
-      }
-      const int nlid = total + 1;
-      __syncthreads();
+      const int nlid = sh_nlid + 1;
       for (int q = tid; q < npad; q += kSimThreads) {
         const uint16_t s = tdoc[q];
         tdoc[q] = s == 0xFFFF ? (uint16_t)0 : (uint16_t)uent[s].y;
