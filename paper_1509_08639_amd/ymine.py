@@ -340,7 +340,9 @@ def mine_bidirectional(ctx: Context, lex_fwd: Lexicon, lex_rev: Lexicon, corpus,
 
 
 def set_tuning(ctx: Context, sim_kernel: int, item_rows: int, nw_pairs_per_group: int):
-    """ym_set_tuning."""
+    """ym_set_tuning: similarity kernel (1 lanes, 2 lanes with split reads of
+    long target sentences, 0 bit-sliced tiles), source rows per work item (64,
+    128, 256), NW pairs per workgroup (1, 2, 4).  No choice changes a result."""
     t = Tuning(sim_kernel, item_rows, nw_pairs_per_group)
     _check(lib().ym_set_tuning(ctx.h, C.byref(t)))
 
