@@ -71,6 +71,28 @@ __global__ __launch_bounds__(256) void score_table_kernel(float w0, float w1, fl
 // translation record: up to four target ids inline (-1 padded), or
 // {-2, offset, count, 0} for a key with more than four (read from the value
 // array when used).
+// A key's translation record: its targets inline (-1 padded) when it has at
+// most four, else {-2, offset, count, 0} into the value array.
+__device__ __forceinline__ int4 lex_record(int c, int32_t o, const int32_t *vals) {
+  int4 r = make_int4(-1, -1, -1, -1);
+  if (c > 4) {
+    r = make_int4(-2, o, c, 0);
+  } else {
+    if (c > 0) r.x = vals[o];
+    if (c > 1) r.y = vals[o + 1];
+    if (c > 2) r.z = vals[o + 2];
+    if (c > 3) r.w = vals[o + 3];
+  }
+  return r;
+}
+
+// The dense table: record of key k at index k (other ids keep -1 x 4).
+__global__ __launch_bounds__(256) void lex_dense_kernel(const int32_t *keys, const int32_t *cnts, const int64_t *offs,
+                                                        const int32_t *vals, int64_t n, int4 *dense) {
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (k < n) dense[keys[k]] = lex_record(cnts[k], (int32_t)offs[k], vals);
+}
+
 __global__ __launch_bounds__(256) void lex_insert_kernel(const int32_t *keys, const int32_t *cnts,
                                                          const int64_t *offs, const int32_t *vals, int64_t n,
                                                          int4 *slots, uint32_t mask, int shift) {
@@ -85,16 +107,7 @@ __global__ __launch_bounds__(256) void lex_insert_kernel(const int32_t *keys, co
       const int32_t o = (int32_t)offs[k];
       slots[2 * h].y = c;
       slots[2 * h].z = o;
-      int4 r = make_int4(-1, -1, -1, -1);
-      if (c > 4) {
-        r = make_int4(-2, o, c, 0);
-      } else {
-        if (c > 0) r.x = vals[o];
-        if (c > 1) r.y = vals[o + 1];
-        if (c > 2) r.z = vals[o + 2];
-        if (c > 3) r.w = vals[o + 3];
-      }
-      slots[2 * h + 1] = r;
+      slots[2 * h + 1] = lex_record(c, o, vals);
       return;
     }
     h = (h + 1) & mask;
@@ -102,11 +115,31 @@ __global__ __launch_bounds__(256) void lex_insert_kernel(const int32_t *keys, co
 }
 
 // Translations of every source token of a batch, resolved once per call
-// (the slot's record; -1 x 4 for ids that are not keys).  Each thread takes
-// four tokens 256 apart, so four independent probe chains are in flight.
+// (the key's record; -1 x 4 for ids that are not keys): one read of the
+// lexicon's dense table when it has one, else a hash lookup.  Each thread
+// takes four tokens 256 apart, so four independent reads or probe chains are
+// in flight.
 constexpr int kTransPerThread = 4;
 __global__ __launch_bounds__(256) void translate_kernel(const int32_t *tok, int64_t n, LexDev L, int4 *out) {
   const int64_t base = (int64_t)blockIdx.x * (256 * kTransPerThread) + threadIdx.x;
+  if (L.dense) {
+    int32_t y[kTransPerThread];
+#pragma unroll
+    for (int u = 0; u < kTransPerThread; u++) {
+      const int64_t k = base + 256 * u;
+      y[u] = k < n ? tok[k] : -1;
+    }
+    int4 r[kTransPerThread];
+#pragma unroll
+    for (int u = 0; u < kTransPerThread; u++)
+      r[u] = (y[u] >= 0 && y[u] < L.dense_n) ? L.dense[y[u]] : make_int4(-1, -1, -1, -1);
+#pragma unroll
+    for (int u = 0; u < kTransPerThread; u++) {
+      const int64_t k = base + 256 * u;
+      if (k < n) out[k] = r[u];
+    }
+    return;
+  }
   int32_t x[kTransPerThread];
   uint32_t h[kTransPerThread];
   int4 s[kTransPerThread], t[kTransPerThread];
@@ -1862,6 +1895,14 @@ hipError_t launch_lex_insert(const int32_t *keys, const int32_t *cnts, const int
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(lex_insert_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, keys, cnts, offs, vals,
                      n, slots, mask, shift);
+  return hipGetLastError();
+}
+
+hipError_t launch_lex_dense(const int32_t *keys, const int32_t *cnts, const int64_t *offs, const int32_t *vals, int64_t n,
+                            int4 *dense, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(lex_dense_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, keys, cnts, offs, vals, n,
+                     dense);
   return hipGetLastError();
 }
 

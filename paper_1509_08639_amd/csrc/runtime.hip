@@ -250,6 +250,8 @@ struct ym_lexicon {
   int32_t shift = 0;
   int64_t n_keys = 0, n_pairs = 0;
   int32_t max_fanout = 0;
+  int4 *dense = nullptr;  // records of ids 0 .. dense_n - 1 (all keys below kDenseKeys)
+  int32_t dense_n = 0;
 };
 
 extern "C" {
@@ -408,11 +410,22 @@ ym_status ym_lexicon_load(ym_ctx *c, const int32_t *src_ids, const int64_t *off,
   if (e == hipSuccess)
     e = launch_lex_insert((const int32_t *)dkeys, (const int32_t *)dcnts, (const int64_t *)doffs, L->vals,
                           (int64_t)keys.size(), L->slots, L->mask, L->shift, c->stream);
+  // the dense table, when every key is small (else the batches get a translation pass)
+  if (e == hipSuccess && !keys.empty() && keys.back() < kDenseKeys &&
+      hipMalloc(&L->dense, (size_t)(keys.back() + 1) * sizeof(int4)) == hipSuccess) {
+    L->dense_n = keys.back() + 1;
+    e = hipMemsetAsync(L->dense, 0xFF, (size_t)L->dense_n * sizeof(int4), c->stream);  // -1 x 4: no translation
+    if (e == hipSuccess)
+      e = launch_lex_dense((const int32_t *)dkeys, (const int32_t *)dcnts, (const int64_t *)doffs, L->vals,
+                           (int64_t)keys.size(), L->dense, c->stream);
+  }
+  (void)hipGetLastError();  // a failed dense allocation only means no dense table
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   cleanup();
   if (e != hipSuccess) {
     hipFree(L->slots);
     hipFree(L->vals);
+    if (L->dense) hipFree(L->dense);
     delete L;
     return hip_fail(e, "lexicon upload");
   }
@@ -426,6 +439,7 @@ void ym_lexicon_free(ym_lexicon *L) {
   hipDeviceSynchronize();  // no kernel may still read the table
   hipFree(L->slots);
   hipFree(L->vals);
+  if (L->dense) hipFree(L->dense);
   delete L;
 }
 
@@ -479,6 +493,8 @@ LexDev lex_dev(const ym_lexicon *L) {
   d.vals = L->vals;
   d.mask = L->mask;
   d.shift = L->shift;
+  d.dense = L->dense;
+  d.dense_n = L->dense_n;
   return d;
 }
 

@@ -80,7 +80,14 @@ struct LexDev {
   const int32_t *vals;
   uint32_t mask;
   int32_t shift;
+  const int4 *dense;  // translation record of every id below dense_n (nullptr: none)
+  int32_t dense_n;
 };
+
+// Lexicons whose keys are all below this get a dense record table too (16
+// bytes per id, 256 MB at most): the translation pass then reads a token's
+// record directly instead of probing the hash table.
+constexpr int32_t kDenseKeys = 1 << 24;
 
 struct SimArgs {
   const SimItem *items;
@@ -121,6 +128,8 @@ struct NwArgs {
 };
 
 // Launch wrappers (kernels.hip).
+hipError_t launch_lex_dense(const int32_t *keys, const int32_t *cnts, const int64_t *offs, const int32_t *vals, int64_t n,
+                            int4 *dense, hipStream_t st);
 hipError_t launch_lex_insert(const int32_t *keys, const int32_t *cnts, const int64_t *offs, const int32_t *vals,
                              int64_t n, int4 *slots, uint32_t mask, int shift, hipStream_t st);
 hipError_t launch_translate(const int32_t *tok, int64_t n, const LexDev &L, int4 *out, hipStream_t st);

@@ -92,6 +92,19 @@ def test_similarity_long_sentences(ym, ctx, ctx_split, O, split):
     _similarity_check(ym, ctx_split if split else ctx, O, lex, c, np.array([-2.0, 3.0, 2.5, 0.75], np.float32))
 
 
+def test_similarity_key_ids_beyond_dense_table(ym, ctx, O):
+    # a key of 2^25: the lexicon gets no dense record table, so the
+    # translation pass probes the hash table
+    lex = parity.random_lexicon(12, vocab=300)
+    big = 1 << 25
+    lex2 = synth.Lexicon(np.concatenate([lex.src_ids, [big]]).astype(np.int32),
+                         np.concatenate([lex.off, [lex.off[-1] + 2]]).astype(np.int64),
+                         np.concatenate([lex.tgt_ids, [5, 7]]).astype(np.int32))
+    c = parity.random_corpus(12, n_pairs=10, nmax=60, mmax=80, lmax_src=40, lmax_tgt=40, vocab=300)
+    c.src_tok[::7] = big
+    _similarity_check(ym, ctx, O, lex2, c, np.array([-2.0, 3.0, 2.5, 0.75], np.float32))
+
+
 @pytest.mark.parametrize("split", [False, True])
 def test_similarity_chunk_boundaries(ym, ctx, ctx_split, O, split):
     # target sentences near the 1024-token chunk limit and many short ones
