@@ -1,13 +1,21 @@
 // Device kernels of libymine for gfx950 (CDNA4, wave64).
 //
-//   lex_insert_kernel    builds the HBM-resident lexicon hash (session setup)
+//   lex_insert_kernel,
+//   lex_dense_kernel     build the HBM-resident lexicon hash and, for small
+//                        key ranges, the dense record table (session setup)
 //   score_table_kernel   sentence-pair score for every (a, b, m_s, m_t) with
 //                        a, b < 64, from the current classifier weights
-//   sim_kernel           (a) sentence-pair score matrix of each document pair
-//   nw_kernel            (b) Needleman-Wunsch forward pass, traceback and
+//   translate_kernel     translation record of every source token of a batch
+//   sim_kernel,
+//   sim_tile_kernel      (a) sentence-pair score matrix of each document pair
+//   nw_kernel,
+//   nw_big_kernel        (b) Needleman-Wunsch forward pass, traceback and
 //                        threshold filter of each document pair
 //   scan_kernel,
 //   compact_kernel       per-pair counts -> CSR offsets, slot -> CSR copy
+//   tune_count_kernel,
+//   merge_bi_kernel      parameter sweep counts; bidirectional union
+//   relayout_kernel      row-major <-> strip-diagonal scores (parity entries)
 //
 // Floating point: the score is built from correctly rounded float divides,
 // products and sums in a fixed order (no contraction; built with
