@@ -425,7 +425,8 @@ __global__ __launch_bounds__(kSimThreads, 3) void sim_kernel(SimArgs a) {
 
   for (int64_t item = blockIdx.x; item < a.n_items; item += gridDim.x) {
     const SimItem it = a.items[item];
-    const PairDesc d = a.descs[it.pair];
+    PairDesc d;  // the descriptor fields the item carries
+    d.n = it.n, d.m = it.m, d.src_sent0 = it.src_sent0, d.tgt_sent0 = it.tgt_sent0, d.s_off = it.s_off, d.rm_off = it.rm_off;
     const int n = d.n, m = d.m;
     if (m <= 0 || it.i1 <= it.i0) continue;
     const int64_t *toffs = a.tgt_sent_off + d.tgt_sent0;
@@ -1159,7 +1160,8 @@ __global__ __launch_bounds__(kTileThreads) void sim_tile_kernel(SimArgs a) {
 
   for (int64_t item = blockIdx.x; item < a.n_items; item += gridDim.x) {
     const SimItem it = a.items[item];
-    const PairDesc d = a.descs[it.pair];
+    PairDesc d;  // the descriptor fields the item carries
+    d.n = it.n, d.m = it.m, d.src_sent0 = it.src_sent0, d.tgt_sent0 = it.tgt_sent0, d.s_off = it.s_off, d.rm_off = it.rm_off;
     const int m = d.m;
     if (m <= 0 || it.i1 <= it.i0) continue;
     const int64_t *toffs = a.tgt_sent_off + d.tgt_sent0;

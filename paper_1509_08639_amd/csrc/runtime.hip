@@ -217,7 +217,13 @@ void Chunk::fill_host(const int64_t *sdo, const int64_t *tdo, char *host) const 
         x.pair = (int32_t)(p - p0);
         x.i0 = (int32_t)i0;
         x.i1 = (int32_t)std::min<int64_t>(n, i0 + item_rows);
+        x.n = d.n;
+        x.m = d.m;
         x.pad = 0;
+        x.src_sent0 = d.src_sent0;
+        x.tgt_sent0 = d.tgt_sent0;
+        x.s_off = d.s_off;
+        x.rm_off = d.rm_off;
       }
     moff[p - p0] = mv;
     mv += n + m;

@@ -70,7 +70,9 @@ struct PairDesc {
 struct SimItem {
   int32_t pair;
   int32_t i0, i1;
-  int32_t pad;
+  int32_t n, m;  // the pair's fields the similarity kernel reads, copied so
+  int32_t pad;   // that an item is one load (no dependent descriptor load)
+  int64_t src_sent0, tgt_sent0, s_off, rm_off;
 };
 
 // Lexicon as resident in HBM: open-addressing table of {key, count, offset, 0}
