@@ -88,7 +88,10 @@ const char *ym_version(void);
  * off[0] = 0, off non-decreasing; a key may repeat (its sets are merged) and
  * target ids may repeat (they are a set).  The lexicon is normalised on the
  * host, copied to HBM and stays resident until ym_lexicon_free (the
- * classifier's data are loaded once per session, Section 4).
+ * classifier's data are loaded once per session, Section 4).  In HBM it is a
+ * hash table over the keys and, when every key is below 2^24, also a table of
+ * 16 bytes per id up to the largest key (at most 256 MB), which makes the
+ * per-batch translation of source tokens a direct read.
  * Errors: YM_EINVAL for negative ids, bad offsets or a key with more than
  * YM_MAX_FANOUT distinct targets; YM_ENOMEM / YM_EDEVICE. */
 ym_status ym_lexicon_load(ym_ctx *ctx, const int32_t *src_ids, const int64_t *off, const int32_t *tgt_ids,
