@@ -202,6 +202,18 @@ def test_device_and_per_pair_forms_match(ym, ctx, O):
     for r in (b, d, e):
         for k in a:
             assert np.array_equal(a[k], r[k]), k
+    # passes back to back on a second stream, two miners interleaved, no host
+    # wait between them (plan uploads on the context's side stream, one
+    # staging buffer)
+    import torch
+    s2 = torch.cuda.Stream()
+    dm.run(w, -0.2, 0.5, stream=s2.cuda_stream)
+    dm2.run(w, -0.2, 0.5, stream=s2.cuda_stream)
+    dm.run(w, -0.2, 0.5, stream=s2.cuda_stream)
+    s2.synchronize()
+    for r in (dm.result(), dm2.result()):
+        for k in a:
+            assert np.array_equal(a[k], r[k]), k
 
 
 def test_mine_ragged_edges_end_to_end(ym, ctx, O):
