@@ -393,6 +393,7 @@ __device__ __forceinline__ int64_t readlane64(int64_t v, int k) {
 }
 
 static_assert(kMaxItemRows / kSimWaves <= 64, "one lane per row of a wave");
+constexpr int kQuadBits = 15;  // source positions per 16-bit field of a four-row step (bit 15: hit bit)
 
 // kHelp: chunks holding target sentences of more than 32 tokens use the lanes
 // they leave over to split the reads (below).  A separate instantiation,
@@ -431,19 +432,64 @@ __global__ __launch_bounds__(kSimThreads, 3) void sim_kernel(SimArgs a) {
     if (m <= 0 || it.i1 <= it.i0) continue;
     const int64_t *toffs = a.tgt_sent_off + d.tgt_sent0;
     const int64_t *soffs = a.src_sent_off + d.src_sent0;
-    // this wave's source rows and their token ranges (lane k: row k).  Wave
-    // wv takes rows i0 + 2 wv + 8 q and the row after (q = 0, 1, ...), so the
-    // two rows of a step are adjacent (items start on 64-row strips).
-    auto row_of = [&](int k) { return it.i0 + 2 * wv + 2 * kSimWaves * (k >> 1) + (k & 1); };
+    // This wave's source rows are rows i0 + 2 wv + 8 q and the row after (q =
+    // 0, 1, ...; items start on 64-row strips, so the two are adjacent).
+    // Kernel 1 takes them in that order, two per step (a longer row alone).
+    // Kernel 2 first orders them by length class: rows of at most 15 tokens
+    // go four to a step (a 16-bit field each in the 8-byte mask entry: 15
+    // position bits and the hit bit), rows of 16-31 tokens two to a step (a
+    // 32-bit field each), longer rows one to a step (the whole entry).  Lane k
+    // holds wave-row k: its first token, and its length (saturated at 2^24 -
+    // 1) | (row - i0) << 24.
     const int nrows = 2 * ((it.i1 - it.i0) / (2 * kSimWaves)) + min(2, max(0, (it.i1 - it.i0) % (2 * kSimWaves) - 2 * wv));
     int64_t rsb = 0;
-    int rlen = 0;
-    if (lane < nrows) {
-      const int ii = row_of(lane);
-      rsb = clamp64(soffs[ii], 0, a.n_src_tok);
-      const int64_t se = clamp64(soffs[ii + 1], rsb, a.n_src_tok);
-      rlen = (int)min(se - rsb, (int64_t)0x7fffffff);
+    int rinf = 0;
+    int nQ = 0, nP = nrows, nL = 0;  // wave-rows [0, nQ) four per step, then nP two per step, then nL alone
+    {
+      const int row = it.i0 + 2 * wv + 2 * kSimWaves * (lane >> 1) + (lane & 1);
+      int64_t sb = 0, len = 0;
+      if (lane < nrows) {
+        sb = clamp64(soffs[row], 0, a.n_src_tok);
+        len = clamp64(soffs[row + 1], sb, a.n_src_tok) - sb;
+      }
+      if constexpr (kHelp) {
+        const int inf = (int)min(len, (int64_t)0xFFFFFF) | ((row - it.i0) << 24);
+        const int cls = lane >= nrows ? 3 : len <= kQuadBits ? 0 : len <= kPosBits ? 1 : 2;
+        const uint64_t mQ = __ballot(cls == 0), mP = __ballot(cls == 1), mL = __ballot(cls == 2);
+        nQ = __popcll(mQ), nP = __popcll(mP), nL = __popcll(mL);
+        const uint64_t below = (1ull << lane) - 1;
+        const int dst = cls == 0 ? __popcll(mQ & below)
+                      : cls == 1 ? nQ + __popcll(mP & below)
+                      : cls == 2 ? nQ + nP + __popcll(mL & below)
+                                 : lane;  // a permutation of the 64 lanes
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_permute(dst << 2, (int)(uint32_t)sb);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_permute(dst << 2, (int)(uint32_t)(sb >> 32));
+        rsb = (int64_t)(((uint64_t)hi << 32) | lo);
+        rinf = __builtin_amdgcn_ds_permute(dst << 2, inf);
+      } else {  // kernel 1: lane k holds row k's first token and length
+        rsb = sb;
+        rinf = (int)min(len, (int64_t)0x7fffffff);
+      }
     }
+    // row index, first token and length of wave-row k (wave-uniform k)
+    auto row_of = [&](int k) {
+      if constexpr (kHelp)
+        return it.i0 + (int)((uint32_t)__builtin_amdgcn_readlane(rinf, k) >> 24);
+      else
+        return it.i0 + 2 * wv + 2 * kSimWaves * (k >> 1) + (k & 1);
+    };
+    auto rinfo = [&](int k, int64_t &sb, int &len) {
+      sb = readlane64(rsb, k);
+      if constexpr (kHelp) {
+        len = __builtin_amdgcn_readlane(rinf, k) & 0xFFFFFF;
+        if (len == 0xFFFFFF) {  // a saturated length: read it again
+          const int i = row_of(k);
+          len = (int)min(clamp64(soffs[i + 1], sb, a.n_src_tok) - sb, (int64_t)0x7fffffff);
+        }
+      } else {
+        len = __builtin_amdgcn_readlane(rinf, k);
+      }
+    };
 
     for (int j0 = 0; j0 < m;) {
       if (tid < 64) chunk_end(toffs, j0, m, a.n_tgt_tok, &sh_j1, sh_ends);
@@ -604,27 +650,34 @@ __global__ __launch_bounds__(kSimThreads, 3) void sim_kernel(SimArgs a) {
       // Combine a group's partial results (two masks OR-ed, one packed sum
       // added) with an xor-style butterfly; afterwards every lane of a group
       // holds the group's totals.
-      auto butterfly = [&](uint32_t &o0, uint32_t &o1, uint32_t &sp) {
+      auto butterfly = [&](uint32_t &o0, uint32_t &o1, uint32_t &sp, uint32_t *sq) {
+        uint32_t sq0 = sq ? *sq : 0u;
         if (maxgs > 1) {
           const uint32_t a0 = dpp_mov<0xB1>(o0), a1 = dpp_mov<0xB1>(o1), b = dpp_mov<0xB1>(sp);
-          if ((grp >> 8) > 1u) o0 |= a0, o1 |= a1, sp += b;
+          const uint32_t c = sq ? dpp_mov<0xB1>(sq0) : 0u;
+          if ((grp >> 8) > 1u) o0 |= a0, o1 |= a1, sp += b, sq0 += c;
         }
         if (maxgs > 2) {
           const uint32_t a0 = dpp_mov<0x4E>(o0), a1 = dpp_mov<0x4E>(o1), b = dpp_mov<0x4E>(sp);
-          if ((grp >> 8) > 2u) o0 |= a0, o1 |= a1, sp += b;
+          const uint32_t c = sq ? dpp_mov<0x4E>(sq0) : 0u;
+          if ((grp >> 8) > 2u) o0 |= a0, o1 |= a1, sp += b, sq0 += c;
         }
         if (maxgs > 4) {
           const uint32_t a0 = dpp_mov<0x141>(o0), a1 = dpp_mov<0x141>(o1), b = dpp_mov<0x141>(sp);
-          if ((grp >> 8) > 4u) o0 |= a0, o1 |= a1, sp += b;
+          const uint32_t c = sq ? dpp_mov<0x141>(sq0) : 0u;
+          if ((grp >> 8) > 4u) o0 |= a0, o1 |= a1, sp += b, sq0 += c;
         }
         if (maxgs > 8) {
           const uint32_t a0 = dpp_mov<0x140>(o0), a1 = dpp_mov<0x140>(o1), b = dpp_mov<0x140>(sp);
-          if ((grp >> 8) > 8u) o0 |= a0, o1 |= a1, sp += b;
+          const uint32_t c = sq ? dpp_mov<0x140>(sq0) : 0u;
+          if ((grp >> 8) > 8u) o0 |= a0, o1 |= a1, sp += b, sq0 += c;
         }
         for (int dd = 16; dd < maxgs; dd <<= 1) {
           const uint32_t a0 = __shfl_xor(o0, dd), a1 = __shfl_xor(o1, dd), b = __shfl_xor(sp, dd);
-          if ((uint32_t)dd < (grp >> 8)) o0 |= a0, o1 |= a1, sp += b;
+          const uint32_t c = sq ? (uint32_t)__shfl_xor((int)sq0, dd) : 0u;
+          if ((uint32_t)dd < (grp >> 8)) o0 |= a0, o1 |= a1, sp += b, sq0 += c;
         }
+        if (sq) *sq = sq0;
       };
       // two-row step: position masks of both rows (hit bit 31) and hit counts
       // -> m_s and m_t of both rows at lane = sentence
@@ -634,10 +687,28 @@ __global__ __launch_bounds__(kSimThreads, 3) void sim_kernel(SimArgs a) {
           return;
         }
         uint32_t sp = t0 | (t1 << 16);  // each count <= kTcap < 2^11
-        butterfly(o0, o1, sp);
+        butterfly(o0, o1, sp, nullptr);
         const uint32_t pk = __popc(o0 & ~kHitBit) | (__popc(o1 & ~kHitBit) << 5) | ((sp & 0x7FFu) << 10) | (((sp >> 16) & 0x7FFu) << 21);
         const uint32_t g = (uint32_t)__shfl((int)pk, (int)(grp & 0xFFu));
         ms0 = g & 31u, ms1 = (g >> 5) & 31u, mt0 = (g >> 10) & 0x7FFu, mt1 = g >> 21;
+      };
+      // four-row step: fields of rows 0, 1 in o0 and 2, 3 in o1 (15 position
+      // bits and the hit bit each); hit counts of rows 0, 1 in the 16-bit
+      // halves of h0, of rows 2, 3 in h1
+      auto counts4 = [&](uint32_t o0, uint32_t o1, uint32_t h0, uint32_t h1, int *ms, int *mt) {
+        if (helped) {
+          butterfly(o0, o1, h0, &h1);
+          const uint32_t pa = h0 | ((uint32_t)__popc(o0 & 0x7FFFu) << 11) | ((uint32_t)__popc(o0 & 0x7FFF0000u) << 27);
+          const uint32_t pb = h1 | ((uint32_t)__popc(o1 & 0x7FFFu) << 11) | ((uint32_t)__popc(o1 & 0x7FFF0000u) << 27);
+          const uint32_t ga = (uint32_t)__shfl((int)pa, (int)(grp & 0xFFu));
+          const uint32_t gb = (uint32_t)__shfl((int)pb, (int)(grp & 0xFFu));
+          ms[0] = (ga >> 11) & 15u, ms[1] = ga >> 27, mt[0] = ga & 0x7FFu, mt[1] = (ga >> 16) & 0x7FFu;
+          ms[2] = (gb >> 11) & 15u, ms[3] = gb >> 27, mt[2] = gb & 0x7FFu, mt[3] = (gb >> 16) & 0x7FFu;
+          return;
+        }
+        ms[0] = __popc(o0 & 0x7FFFu), ms[1] = __popc(o0 & 0x7FFF0000u);
+        ms[2] = __popc(o1 & 0x7FFFu), ms[3] = __popc(o1 & 0x7FFF0000u);
+        mt[0] = h0 & 0xFFFFu, mt[1] = h0 >> 16, mt[2] = h1 & 0xFFFFu, mt[3] = h1 >> 16;
       };
       // one-row pass: a 64-bit position mask (hit bit 63) and the hit count
       auto counts1 = [&](uint32_t o0, uint32_t o1, uint32_t t, int &ms, int &mt) {
@@ -645,7 +716,7 @@ __global__ __launch_bounds__(kSimThreads, 3) void sim_kernel(SimArgs a) {
           ms = __popc(o0) + __popc(o1 & ~kHitBit), mt = (int)t;
           return;
         }
-        butterfly(o0, o1, t);
+        butterfly(o0, o1, t, nullptr);
         const uint32_t pk = (__popc(o0) + __popc(o1 & ~kHitBit)) | (t << 6);
         const uint32_t g = (uint32_t)__shfl((int)pk, (int)(grp & 0xFFu));
         ms = g & 63u, mt = g >> 6;
@@ -700,8 +771,9 @@ __global__ __launch_bounds__(kSimThreads, 3) void sim_kernel(SimArgs a) {
       // positions (longer sentences take further passes, position bits only).
       auto single_row = [&](const int k) {
         const int i = row_of(k);
-        const int64_t sb = readlane64(rsb, k);
-        const int ai = __builtin_amdgcn_readlane(rlen, k);
+        int64_t sb;
+        int ai;
+        rinfo(k, sb, ai);
         const int4 cur = lane < ai ? a.trans[sb + lane] : make_int4(-1, -1, -1, -1);
         unsigned long long *Mq = reinterpret_cast<unsigned long long *>(Mx);
         constexpr int kPass = 63;
@@ -777,10 +849,19 @@ __global__ __launch_bounds__(kSimThreads, 3) void sim_kernel(SimArgs a) {
       // first word of each entry and row k + 1 the second, so one 8-byte read
       // per target token serves both rows.  The translations of the next two
       // rows are fetched while these are worked on.
+      // two-row steps take wave-rows k and k + 1 of [nQ, nP2)
+      const int nP2 = nQ + nP;
       auto fetch2 = [&](int k) -> int4 {
-        const int64_t b0 = readlane64(rsb, min(k, 63)), b1 = readlane64(rsb, min(k + 1, 63));
-        const int n0 = k < nrows ? __builtin_amdgcn_readlane(rlen, min(k, 63)) : 0;
-        const int n1 = k + 1 < nrows ? __builtin_amdgcn_readlane(rlen, min(k + 1, 63)) : 0;
+        int64_t b0 = 0, b1 = 0;
+        int n0 = 0, n1 = 0;
+        if constexpr (kHelp) {
+          if (k < nP2) rinfo(k, b0, n0);
+          if (k + 1 < nP2) rinfo(k + 1, b1, n1);
+        } else {
+          b0 = readlane64(rsb, min(k, 63)), b1 = readlane64(rsb, min(k + 1, 63));
+          n0 = k < nrows ? __builtin_amdgcn_readlane(rinf, min(k, 63)) : 0;
+          n1 = k + 1 < nrows ? __builtin_amdgcn_readlane(rinf, min(k + 1, 63)) : 0;
+        }
         const int q = lane & 31, len = lane < 32 ? n0 : n1;
         const bool ok = q < len && len <= kPosBits;
         // every lane reads (a valid token's record: clamped), then keeps it or not
@@ -789,13 +870,22 @@ __global__ __launch_bounds__(kSimThreads, 3) void sim_kernel(SimArgs a) {
         return ok ? r : make_int4(-1, -1, -1, -1);
       };
       auto pair_rows = [&](const int k, const int4 cur, Pend &pend) {
-        const int ai0 = __builtin_amdgcn_readlane(rlen, k);
-        const bool has1 = k + 1 < nrows;
-        const int ai1 = has1 ? __builtin_amdgcn_readlane(rlen, k + 1) : 0;
-        if (ai0 > kPosBits || ai1 > kPosBits) {
-          single_row(k);
-          if (has1) single_row(k + 1);
-          return;
+        const bool has1 = k + 1 < nP2;
+        int ai0, ai1 = 0;
+        if constexpr (kHelp) {
+          int64_t sbx;
+          rinfo(k, sbx, ai0);
+          if (has1) rinfo(k + 1, sbx, ai1);
+        } else {
+          ai0 = __builtin_amdgcn_readlane(rinf, k);
+          ai1 = has1 ? __builtin_amdgcn_readlane(rinf, k + 1) : 0;
+        }
+        if constexpr (!kHelp) {  // kernel 2's row classes leave no long row here
+          if (ai0 > kPosBits || ai1 > kPosBits) {
+            single_row(k);
+            if (has1) single_row(k + 1);
+            return;
+          }
         }
         const int half = lane >> 5, q = lane & 31;
         const int aih = half ? ai1 : ai0;
@@ -866,12 +956,15 @@ __global__ __launch_bounds__(kSimThreads, 3) void sim_kernel(SimArgs a) {
           }
         }
         wave_sync();
-        const int i = row_of(k);
+        const int i = row_of(k), i1 = has1 ? row_of(k + 1) : -1;
         int off0, off1 = -1;
         const float sv0 = score_cell(i, ai0, ms0, mc0, off0);
         float sv1 = 0.0f;
-        if (has1) sv1 = score_cell(i + 1, ai1, ms1, mc1, off1);
-        const bool pairable = has1 && ((min(64, n - ((i >> 6) << 6)) & 1) == 0);  // strip of even R
+        if (has1) sv1 = score_cell(i1, ai1, ms1, mc1, off1);
+        // rows i and i + 1 (i even) of a strip with an even row count: 8-byte
+        // stores (kernel 1's two rows always are i and i + 1 with i even)
+        const bool adjacent = kHelp ? (i1 == i + 1 && (i & 1) == 0) : has1;
+        const bool pairable = adjacent && ((min(64, n - ((i >> 6) << 6)) & 1) == 0);
         const float left_v = shift_up_one_lane(sv1);  // lane c: cell (i + 1, c - 1)
         const int left_o = __shfl_up(off1, 1);
         const bool paired = pairable && lane >= 1 && off0 >= 0 && left_o >= 0;
@@ -884,17 +977,160 @@ __global__ __launch_bounds__(kSimThreads, 3) void sim_kernel(SimArgs a) {
         pend.oB = (off1 >= 0 && !right_pairs) ? off1 : -1;
         pend.vB = sv1;
       };
-      int4 bufA = fetch2(0), bufB;
-      Pend qa, qb;
-      for (int k = 0; k < nrows; k += 4) {
-        bufB = fetch2(k + 2);
-        pair_rows(k, bufA, qa);
-        if (k + 2 >= nrows) break;
-        bufA = fetch2(k + 4);
-        pair_rows(k + 2, bufB, qb);
+      if constexpr (kHelp) {
+        // Four rows at a time (all of at most 15 tokens): lanes 16 r + q hold
+        // position q of row r, and row r marks its 16-bit field of the entry
+        // (half r & 1 of word r >> 1): position bits 0-14, hit bit 15.
+        const int cq = (nQ + 3) >> 2;  // four-row units: wave-rows 4 t ..
+        auto fetch4 = [&](int t) -> int4 {
+          const int r = lane >> 4, q = lane & 15;
+          int64_t sbr = 0;
+          int len = 0;
+  #pragma unroll
+          for (int rr = 0; rr < 4; rr++) {
+            if (t < cq && 4 * t + rr < nQ) {
+              int64_t b;
+              int l;
+              rinfo(4 * t + rr, b, l);
+              if (r == rr) sbr = b, len = l;
+            }
+          }
+          const bool ok = q < len && len <= kQuadBits;
+          const int64_t at = ok ? sbr + q : 0;
+          const int4 rec = a.trans[at];
+          return ok ? rec : make_int4(-1, -1, -1, -1);
+        };
+        struct PendQ {
+          int o[4] = {-1, -1, -1, -1};
+          float v[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        };
+        auto flushQ = [&](PendQ &q) {
+  #pragma unroll
+          for (int rr = 0; rr < 4; rr++)
+            if (q.o[rr] >= 0) Sb[q.o[rr]] = q.v[rr];
+        };
+        auto quad_rows = [&](const int t, const int4 cur, PendQ &pend) {
+          const int r = lane >> 4, q = lane & 15;
+          const bool far = cur.x == -2;  // more than four translations
+          const int4 lid = u2_lid4(uent, far ? make_int4(-1, -1, -1, -1) : cur);
+          const int l0 = lid.x, l1 = lid.y, l2 = lid.z, l3 = lid.w;
+          uint32_t *Mh = Mx + (r >> 1);  // this row's word of entry l: Mh[2 l]
+          const uint32_t bits = ((1u << kQuadBits) | (1u << q)) << (16 * (r & 1));
+          if (far) {
+            for (int e = 0; e < cur.z; e++) {
+              const int l = u2_lid(uent, a.lex.vals[cur.y + e]);
+              if (l) atomicOr(&Mh[2 * l], bits);
+            }
+          } else {
+            if (l0) atomicOr(&Mh[2 * l0], bits);
+            if (l1) atomicOr(&Mh[2 * l1], bits);
+            if (l2) atomicOr(&Mh[2 * l2], bits);
+            if (l3) atomicOr(&Mh[2 * l3], bits);
+          }
+          wave_sync();
+          uint32_t ox = 0, oy = 0, hx = 0, hy = 0;
+  #pragma unroll
+          for (int g = 0; g < kRegTok / 8; g++) {
+            if (2 * g < ng) {
+              uint2 w[8];
+  #pragma unroll
+              for (int u = 0; u < 8; u++) w[u] = lds_u2_at(ad[8 * g + u]);
+  #pragma unroll
+              for (int u = 0; u < 8; u += 4) {
+                hx += ((w[u].x >> 15) & 0x10001u) + ((w[u + 1].x >> 15) & 0x10001u) + ((w[u + 2].x >> 15) & 0x10001u) +
+                      ((w[u + 3].x >> 15) & 0x10001u);
+                hy += ((w[u].y >> 15) & 0x10001u) + ((w[u + 1].y >> 15) & 0x10001u) + ((w[u + 2].y >> 15) & 0x10001u) +
+                      ((w[u + 3].y >> 15) & 0x10001u);
+                ox |= (w[u].x | w[u + 1].x) | (w[u + 2].x | w[u + 3].x);
+                oy |= (w[u].y | w[u + 1].y) | (w[u + 2].y | w[u + 3].y);
+              }
+            }
+          }
+          for (int k2 = kRegTok; k2 < maxb; k2 += 4) {  // beyond 32 tokens, four ids per read
+            if (k2 < bl) {  // only chunks without helpers get here (rl == bl)
+              const uint2 ids = *reinterpret_cast<const uint2 *>(tp + k2);
+              const uint2 w0 = *reinterpret_cast<const uint2 *>(Mx + 2 * (ids.x & 0xFFFFu));
+              const uint2 w1 = *reinterpret_cast<const uint2 *>(Mx + 2 * (ids.x >> 16));
+              const uint2 w2 = *reinterpret_cast<const uint2 *>(Mx + 2 * (ids.y & 0xFFFFu));
+              const uint2 w3 = *reinterpret_cast<const uint2 *>(Mx + 2 * (ids.y >> 16));
+              hx += ((w0.x >> 15) & 0x10001u) + ((w1.x >> 15) & 0x10001u) + ((w2.x >> 15) & 0x10001u) + ((w3.x >> 15) & 0x10001u);
+              hy += ((w0.y >> 15) & 0x10001u) + ((w1.y >> 15) & 0x10001u) + ((w2.y >> 15) & 0x10001u) + ((w3.y >> 15) & 0x10001u);
+              ox |= (w0.x | w1.x) | (w2.x | w3.x);
+              oy |= (w0.y | w1.y) | (w2.y | w3.y);
+            }
+          }
+          int ms[4], mt[4];
+          counts4(ox, oy, hx, hy, ms, mt);
+          wave_sync();
+          if (far) {
+            for (int e = 0; e < cur.z; e++) {
+              const int l = u2_lid(uent, a.lex.vals[cur.y + e]);
+              if (l) Mh[2 * l] = 0;
+            }
+          } else {
+            if (l0) Mh[2 * l0] = 0;
+            if (l1) Mh[2 * l1] = 0;
+            if (l2) Mh[2 * l2] = 0;
+            if (l3) Mh[2 * l3] = 0;
+          }
+          wave_sync();
+          flushQ(pend);  // this call site's scores of two steps ago
+  #pragma unroll
+          for (int rr = 0; rr < 4; rr++) {
+            pend.o[rr] = -1;
+            if (4 * t + rr < nQ) {
+              int64_t sbx;
+              int ai;
+              rinfo(4 * t + rr, sbx, ai);
+              pend.v[rr] = score_cell(row_of(4 * t + rr), ai, ms[rr], mt[rr], pend.o[rr]);
+            }
+          }
+        };
+
+        // One call site per step kind (code size): the prefetched records and
+        // the two pending sets trade places after every step.
+        {  // four-row units
+          int4 fa = fetch4(0);
+          PendQ pa, pb;
+          for (int t = 0; t < cq; t++) {
+            const int4 fb = fetch4(t + 1);
+            quad_rows(t, fa, pa);
+            fa = fb;
+            const PendQ px = pa;
+            pa = pb;
+            pb = px;
+          }
+          flushQ(pa);
+          flushQ(pb);
+        }
+        {  // two-row units
+          int4 fa = fetch2(nQ);
+          Pend qa, qb;
+          for (int k = nQ; k < nP2; k += 2) {
+            const int4 fb = fetch2(k + 2);
+            pair_rows(k, fa, qa);
+            fa = fb;
+            const Pend qx = qa;
+            qa = qb;
+            qb = qx;
+          }
+          flush(qa);
+          flush(qb);
+        }
+        for (int t = 0; t < nL; t++) single_row(nQ + nP + t);  // one-row units
+      } else {
+        int4 bufA = fetch2(0), bufB;
+        Pend qa, qb;
+        for (int k = 0; k < nrows; k += 4) {
+          bufB = fetch2(k + 2);
+          pair_rows(k, bufA, qa);
+          if (k + 2 >= nrows) break;
+          bufA = fetch2(k + 4);
+          pair_rows(k + 2, bufB, qb);
+        }
+        flush(qa);
+        flush(qb);
       }
-      flush(qa);
-      flush(qb);
       __syncthreads();
       j0 = j1;
     }
