@@ -61,6 +61,14 @@ typedef int32_t ym_status;
 /* Largest number of target ids one lexicon key may translate to. */
 #define YM_MAX_FANOUT 255
 
+/* Size limits of one document pair, checked by every entry point before any
+ * work is enqueued (YM_EINVAL otherwise): at most 2^22 sentences per document
+ * and fewer than 2^31 score slots, about n * (m + 63) for n >= 64 (the
+ * similarity kernels address a pair's scores with 32-bit offsets; n = m =
+ * 46,000 is about the largest square pair).  Host-only, needs no device:
+ * YM_OK if a pair of n source and m target sentences is accepted. */
+ym_status ym_check_pair(int64_t n, int64_t m);
+
 typedef struct ym_ctx ym_ctx;
 typedef struct ym_lexicon ym_lexicon;
 typedef struct ym_server ym_server;
@@ -185,7 +193,17 @@ typedef struct {
   int32_t *tgt_idx;   /* device [capacity] */
   float *score;       /* device [capacity] */
   float *align_score; /* device [n_pairs] */
+  int32_t *status;    /* device, one int32, may be NULL: 0, or YM_EDEVICE once any
+                         pair of the call could not be completed on the device */
 } ym_device_out;
+
+/* Device failures of this form are reported on the device, since the call
+ * returns before its work runs: a pair whose sweep gives up (a bounded wait of
+ * the pipelined NW sweep of a pair of 448 or more source sentences ran past
+ * its limit) gets align_score NaN and no accepted pairs, and *out->status is
+ * set to YM_EDEVICE (the library clears it to 0 at the start of the call).
+ * The host entry points read these themselves and return YM_EDEVICE; a served
+ * request that fails this way fails alone with YM_EDEVICE. */
 
 /* Output capacity: sum over pairs of min(n, m). */
 int64_t ym_mine_device_capacity(const int64_t *src_doc_off, const int64_t *tgt_doc_off, int64_t n_pairs);
@@ -267,6 +285,14 @@ ym_status ym_get_tuning(ym_ctx *ctx, ym_tuning *tuning);
  * configuration is kept. */
 ym_status ym_autotune(ym_ctx *ctx, const ym_lexicon *lex, const ym_batch *sample, const ym_params *params,
                       int32_t reps, ym_tuning *best, double *best_ms);
+
+/* Failure injection for tests of the error path: the limit, in ticks of the
+ * device's 100 MHz constant clock, of one bounded wait of the pipelined NW
+ * sweep (pairs of 448 or more source sentences).  ticks < 0 restores the
+ * default (20 s); 0 makes every such wait give up at once, so every pair that
+ * needs the pipelined sweep fails with YM_EDEVICE while every kernel still
+ * runs to its end. */
+ym_status ym_set_wait_limit(ym_ctx *ctx, int64_t ticks);
 
 /* ------------------------------------------------------------ kernel timing */
 

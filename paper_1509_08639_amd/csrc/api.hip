@@ -39,6 +39,9 @@ ym_status check_host_batch(const ym_batch *b, HostBatchInfo &info) {
   ym_status s;
   if ((s = check_doc_off(b->src_doc_off, b->n_pairs, "src_doc_off"))) return s;
   if ((s = check_doc_off(b->tgt_doc_off, b->n_pairs, "tgt_doc_off"))) return s;
+  for (int64_t p = 0; p < b->n_pairs; p++)
+    if ((s = check_pair_shape(b->src_doc_off[p + 1] - b->src_doc_off[p], b->tgt_doc_off[p + 1] - b->tgt_doc_off[p], p)))
+      return s;
   info.n_src_sent = b->src_doc_off[b->n_pairs];
   info.n_tgt_sent = b->tgt_doc_off[b->n_pairs];
   if ((s = check_sent_off(b->src_sent_off, info.n_src_sent, "src_sent_off"))) return s;
@@ -100,11 +103,12 @@ size_t min_workspace(const int64_t *sdo, const int64_t *tdo, int64_t n_pairs, in
   return b + 16 * 256 + trans_bytes(n_src_tok);
 }
 
-// Device output buffers of a host-API call, carved from ctx->outb.
+// Device output buffers of a host-API call, carved from ctx->outb, with the
+// call's status word cleared on the context's stream.
 ym_status alloc_outputs(ym_ctx *c, int64_t n_pairs, int64_t cap, ym_device_out &o) {
   const size_t s1 = a256((size_t)(n_pairs + 1) * 8), s2 = a256((size_t)std::max<int64_t>(n_pairs, 1) * 4);
   const size_t s3 = a256((size_t)std::max<int64_t>(cap, 1) * 4);
-  ym_status s = c->outb.reserve(s1 + s2 + 3 * s3);
+  ym_status s = c->outb.reserve(s1 + s2 + 3 * s3 + 256);
   if (s) return s;
   char *p = (char *)c->outb.ptr;
   o.pair_off = (int64_t *)p;
@@ -112,6 +116,19 @@ ym_status alloc_outputs(ym_ctx *c, int64_t n_pairs, int64_t cap, ym_device_out &
   o.src_idx = (int32_t *)(p + s1 + s2);
   o.tgt_idx = (int32_t *)(p + s1 + s2 + s3);
   o.score = (float *)(p + s1 + s2 + 2 * s3);
+  o.status = (int32_t *)(p + s1 + s2 + 3 * s3);
+  const hipError_t e = launch_fill_i32(o.status, 0, 1, c->stream);
+  return e ? hip_fail(e, "status clear") : YM_OK;
+}
+
+// The call's device status word (after the stream has finished its work).
+ym_status read_status(ym_ctx *c, const ym_device_out &o) {
+  int32_t st = 0;
+  hipError_t e = hipMemcpyAsync(&st, o.status, 4, hipMemcpyDeviceToHost, c->stream);
+  if (!e) e = hipStreamSynchronize(c->stream);
+  if (e) return hip_fail(e, "status download");
+  if (st != 0)
+    return fail(YM_EDEVICE, "a pair's pipelined Needleman-Wunsch sweep gave up on a bounded wait (device status %d)", st);
   return YM_OK;
 }
 
@@ -132,6 +149,11 @@ ym_status download_result(ym_ctx *c, int64_t n_pairs, const ym_device_out &o, ym
   if (e) {
     ym_result_free(r);
     return hip_fail(e, "result download");
+  }
+  ym_status st = read_status(c, o);
+  if (st) {
+    ym_result_free(r);
+    return st;
   }
   r->n_out = r->pair_off[n_pairs];
   const size_t k = (size_t)std::max<int64_t>(r->n_out, 1);
@@ -321,6 +343,10 @@ ym_status ym_mine_device(ym_ctx *c, const ym_lexicon *L, const ym_device_batch *
   d.n_tgt_sent = b->tgt_doc_off[b->n_pairs];
   d.n_src_tok = b->n_src_tok;
   d.n_tgt_tok = b->n_tgt_tok;
+  if (out->status) {
+    const hipError_t e = launch_fill_i32(out->status, 0, 1, st);
+    if (e) return hip_fail(e, "status clear");
+  }
   if (b->n_pairs == 0) {
     hipError_t e = hipMemsetAsync(out->pair_off, 0, 8, st);
     return e ? hip_fail(e, "memset") : YM_OK;
@@ -435,6 +461,7 @@ ym_status ym_tune(ym_ctx *c, const ym_lexicon *L, const ym_batch *b, const float
   if (!e) e = hipMemcpyAsync(hc.data(), d_corr, hc.size() * 8, hipMemcpyDeviceToHost, c->stream);
   if (!e) e = hipStreamSynchronize(c->stream);
   if (e) return hip_fail(e, "tune download");
+  if ((s = read_status(c, o))) return s;
   for (size_t k = 0; k < hm.size(); k++) {
     n_mined[k] = (int64_t)hm[k];
     n_correct[k] = (int64_t)hc[k];
@@ -481,6 +508,7 @@ ym_status ym_mine_bidirectional(ym_ctx *c, const ym_lexicon *Lf, const ym_lexico
   int32_t *counts = (int32_t *)((char *)two.ptr + 2 * per);
   ym_device_out o;
   if ((s = alloc_outputs(c, P, 2 * cap, o))) return s;
+  of.status = orv.status = o.status;  // either direction's failure fails the call
   const size_t head = trans_bytes(std::max(info.n_src_tok, info.n_tgt_tok));
   for (int dir = 0; dir < 2; dir++) {
     const int64_t *sdo = dir ? b->tgt_doc_off : b->src_doc_off, *tdo = dir ? b->src_doc_off : b->tgt_doc_off;
@@ -726,6 +754,7 @@ ym_status ym_nw_align(ym_ctx *c, const float *S, const int32_t *n, const int32_t
   if (!e) e = hipStreamSynchronize(c->stream);
   buf.release();
   if (e) return hip_fail(e, "nw download");
+  if ((s = read_status(c, o))) return s;
   if (out) return download_result(c, n_pairs, o, out);
   return YM_OK;
 }

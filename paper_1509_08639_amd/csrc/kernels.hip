@@ -254,12 +254,6 @@ __device__ __forceinline__ float shift_up_one_lane(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x138, 0xF, 0xF, false));
 }
 
-// offset of score (i, c) inside its pair's block (layout: score_slots)
-__device__ __forceinline__ int64_t score_pos(int i, int c, int n, int m) {
-  const int s = i >> 6, l = i & 63;
-  const int R = min(64, n - (s << 6));
-  return (int64_t)s * (m + 63) * 64 + (int64_t)(l + c) * R + l;
-}
 
 // End of the target chunk starting at sentence j0, by the first wave: the
 // largest j1 <= j0 + 64 whose sentences [j0, j1) hold at most kTcap tokens
@@ -1540,23 +1534,27 @@ struct NwPipe {
   int64_t *prog = nullptr;  // LDS slots, one per wave
   int W = 1;
   int *abort = nullptr;  // LDS flag: a wait ran past its time limit
+  uint64_t limit = kNwWaitTicks;  // ticks of the 100 MHz constant counter; 0: give up at once
 };
-
-// Wall-clock limit of one wait (ticks of the constant 100 MHz counter): far
-// above any legitimate wait, which is at most one strip sweep.
-constexpr uint64_t kNwWaitTicks = 2000000000ull;  // 20 s
 
 // Wait until strip `strip` has published at least `cols` columns (or has been
 // finished and its wave moved on).  Wave-uniform; false if the limit was hit.
+// After a give-up every later wait of the workgroup returns false at once, so
+// the waves finish their sweeps (on stale boundary values, every access still
+// inside its arrays) and the pair is reported as failed.
 __device__ __forceinline__ bool nw_wait(const NwPipe &pp, int strip, int cols) {
   int64_t *slot = pp.prog + (strip % pp.W);
+  if (pp.limit == 0) {  // failure injection: every wait gives up
+    __hip_atomic_store(pp.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    return false;
+  }
   const uint64_t t0 = wall_clock64();
   for (;;) {
     const int64_t v = __hip_atomic_load(slot, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
     const int vs = (int)(v >> 32), vc = (int)(uint32_t)v;
     if (vs > strip || (vs == strip && vc >= cols)) return true;
     if (__hip_atomic_load(pp.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) return false;
-    if (wall_clock64() - t0 > kNwWaitTicks) {
+    if (wall_clock64() - t0 > pp.limit) {
       __hip_atomic_store(pp.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       return false;
     }
@@ -1946,9 +1944,10 @@ __global__ __launch_bounds__(64 * NPW) void nw_kernel(NwArgs a) {
 // row per strip boundary), so the strips run as a pipeline lagging about one
 // block plus 64 steps behind each other.  Every wait is for a strip with a
 // smaller index, swept by a wave of the same (co-resident) workgroup, so the
-// pipeline always drains; each wait also ends after kNwWaitTicks (the pair is
-// then reported with no accepted pairs and a NaN score).  After the sweep,
-// wave 0 traces back.
+// pipeline always drains; each wait also ends after a time limit (default
+// kNwWaitTicks), and the pair is then reported with no accepted pairs, a NaN
+// score and the call's status word set, which the host turns into an error.
+// After the sweep, wave 0 traces back.
 __global__ __launch_bounds__(64 * kNwBigWaves) void nw_big_kernel(NwArgs a) {
   __shared__ int64_t prog[kNwBigWaves];
   __shared__ int abort_flag;
@@ -1966,7 +1965,7 @@ __global__ __launch_bounds__(64 * kNwBigWaves) void nw_big_kernel(NwArgs a) {
     uint32_t *dirs = a.dir_scratch + d.dir_off;
     float *rows = a.row_scratch + d.row_off;  // bottom row of strip s at rows + s (m + 1)
     const int nstrips = (d.n + 63) >> 6;
-    const NwPipe pp{prog, kNwBigWaves, &abort_flag};
+    const NwPipe pp{prog, kNwBigWaves, &abort_flag, a.wait_ticks};
     if (d.m <= 0) {  // no target sentence: the boundary alone
       if (threadIdx.x == 0) s_hnm = nw_boundary_only(d.n, d.m, a.gap);
     } else
@@ -1979,11 +1978,12 @@ __global__ __launch_bounds__(64 * kNwBigWaves) void nw_big_kernel(NwArgs a) {
     __syncthreads();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     if (wv == 0) {
-      if (abort_flag) {
+      if (abort_flag) {  // the pair is reported as failed: NaN score, no pairs, status word set
         if (lane == 0) {
           a.counts[p] = 0;
           a.align[a.pair_base + p] = __int_as_float(0x7fc00000);
           if (a.n_moves) a.n_moves[a.pair_base + p] = 0;
+          if (a.status) __hip_atomic_store(a.status, kStatusWaitGaveUp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
       } else {
         nw_finish<false>(a, d, p, dirs, s_hnm);

@@ -114,7 +114,7 @@ static inline int64_t nw_global_row_floats(int64_t n, int64_t m) {
 static inline bool nw_needs_global_row(int64_t n, int64_t m) { return nw_global_row_floats(n, m) > 0; }
 
 size_t pair_bytes(int64_t n, int64_t m) {
-  size_t b = sizeof(PairDesc) + 4 /*count*/ + 8 /*moves off*/;
+  size_t b = sizeof(PairDesc) + 4 /*count*/ + 8 /*moves off*/ + 4 /*NW launch order*/;
   b += (size_t)((n + kMinItemRows - 1) / kMinItemRows) * sizeof(SimItem);  // bound over item sizes
   b += (size_t)score_block(n, m) * 4;
   if (nw_needs_global_dirs(n, m)) b += (size_t)(n * nw_dir_row_words(m)) * 4;
@@ -480,6 +480,15 @@ ym_status ym_profile_read(ym_ctx *c, double ms[4], int64_t launches[4]) {
   return YM_OK;
 }
 
+ym_status ym_check_pair(int64_t n, int64_t m) { return check_pair_shape(n, m, 0); }
+
+ym_status ym_set_wait_limit(ym_ctx *c, int64_t ticks) {
+  if (!c) return fail(YM_EINVAL, "NULL context");
+  std::lock_guard<std::mutex> lk(c->mu);
+  c->nw_wait_ticks = ticks < 0 ? kNwWaitTicks : (uint64_t)ticks;
+  return YM_OK;
+}
+
 ym_status ym_lexicon_stats(const ym_lexicon *L, int64_t *n_keys, int64_t *n_pairs, int32_t *max_fanout) {
   if (!L) return fail(YM_EINVAL, "NULL lexicon");
   if (n_keys) *n_keys = L->n_keys;
@@ -546,14 +555,25 @@ ym_status check_doc_off(const int64_t *o, int64_t n_pairs, const char *what) {
   return YM_OK;
 }
 
+ym_status check_pair_shape(int64_t n, int64_t m, int64_t pair) {
+  if (n < 0 || m < 0) return fail(YM_EINVAL, "pair %lld: negative sentence count", (long long)pair);
+  if (n > kMaxDocSents || m > kMaxDocSents)
+    return fail(YM_EINVAL, "pair %lld: a document has more than %lld sentences", (long long)pair, (long long)kMaxDocSents);
+  if (score_slots(n, m) > kMaxPairSlots)
+    return fail(YM_EINVAL, "pair %lld: %lld x %lld sentences need %lld score slots (at most 2^31 - 4)", (long long)pair,
+                (long long)n, (long long)m, (long long)score_slots(n, m));
+  return YM_OK;
+}
+
 // Split pairs [0, n_pairs) into chunks whose workspace fits `ws_bytes`.
 ym_status plan_chunks(const int64_t *sdo, const int64_t *tdo, int64_t n_pairs, size_t ws_bytes,
                       std::vector<std::pair<int64_t, int64_t>> &chunks) {
   chunks.clear();
   int64_t p = 0;
-  for (int64_t q = 0; q < n_pairs; q++)
-    if (sdo[q + 1] - sdo[q] > kMaxDocSents || tdo[q + 1] - tdo[q] > kMaxDocSents)
-      return fail(YM_EINVAL, "pair %lld: a document has more than %lld sentences", (long long)q, (long long)kMaxDocSents);
+  for (int64_t q = 0; q < n_pairs; q++) {
+    const ym_status st = check_pair_shape(sdo[q + 1] - sdo[q], tdo[q + 1] - tdo[q], q);
+    if (st) return st;
+  }
   while (p < n_pairs) {
     size_t acc = kChunkSlack;
     int64_t q = p;
@@ -664,6 +684,8 @@ ym_status run_chunk(ym_ctx *c, const ym_lexicon *L, const DevBatch &b, const ym_
   n.order = (const int32_t *)(ws + ch.off_order);
   n.n_big = ch.n_big;
   n.n_moves = dbg ? dbg->n_moves_dev : nullptr;
+  n.wait_ticks = c->nw_wait_ticks;
+  n.status = out.status;
   if (n.moves) n.moves += dbg->moves_base;
   {
     KernelTimer kt(c, 1, st);

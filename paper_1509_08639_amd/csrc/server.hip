@@ -15,6 +15,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstdlib>
 #include <cstring>
@@ -194,6 +195,7 @@ ym_status launch_step(ym_server *S, Slot &sl) {
   o.src_idx = (int32_t *)(ob + o1 + o2);
   o.tgt_idx = (int32_t *)(ob + o1 + o2 + o3);
   o.score = (float *)(ob + o1 + o2 + 2 * o3);
+  o.status = nullptr;  // a failed pair is told by its NaN score (finish_step)
   if ((s = run_chunk(S->ctx, S->lex, b, &S->prm, sl.sdo.data(), sl.tdo.data(), ch, ws, o, sl.stream, nullptr,
                      &sl.stage))) {
     abort_capture();
@@ -258,6 +260,10 @@ void finish_step(ym_server *S, Slot &sl, ym_status st) {
       r->status = st;
     } else if (r->cancel) {
       r->state = kCancelled;
+    } else if (std::isnan(al[k])) {  // the pair's pipelined sweep gave up on a bounded wait
+      r->state = kFailed;
+      r->status = YM_EDEVICE;
+      r->error = "the pipelined Needleman-Wunsch sweep gave up on a bounded wait";
     } else {
       const int64_t a = po[k], c = po[k + 1] - po[k];
       ym_result *res = (ym_result *)calloc(1, sizeof(ym_result));
@@ -443,8 +449,7 @@ ym_status ym_submit(ym_server *S, const ym_batch *b, uint64_t *ticket) {
   if ((s = check_doc_off(b->src_doc_off, 1, "src_doc_off")) || (s = check_doc_off(b->tgt_doc_off, 1, "tgt_doc_off")))
     return s;
   const int64_t n = b->src_doc_off[1], m = b->tgt_doc_off[1];
-  if (n > kMaxDocSents || m > kMaxDocSents)
-    return fail(YM_EINVAL, "a document has more than %lld sentences", (long long)kMaxDocSents);
+  if ((s = check_pair_shape(n, m, 0))) return s;
   if (!b->src_sent_off || !b->tgt_sent_off) return fail(YM_EINVAL, "NULL sentence offsets");
   if (b->src_sent_off[0] != 0 || b->tgt_sent_off[0] != 0) return fail(YM_EINVAL, "sentence offsets must start at 0");
   for (int64_t i = 0; i < n; i++) {

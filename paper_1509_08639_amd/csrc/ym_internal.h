@@ -22,7 +22,9 @@ static_assert(kJcap <= kSimThreads && kJcap == 64, "one lane per target sentence
 constexpr int kItemRows = 128;          // source sentences per work item (two 64-row strips)
 constexpr int kMinItemRows = 64, kMaxItemRows = 256;  // range of the tunable rows per similarity item
 constexpr int kMaxSentTokens = 1024;    // longest sentence the host entry points accept
-constexpr int64_t kMaxDocSents = 1 << 22;  // most sentences per document (one score strip stays below 2 GiB)
+// Most sentences per document: one 64-row strip of a pair's scores, which the
+// NW sweep reads through one buffer resource, then stays below 2 GiB.
+constexpr int64_t kMaxDocSents = 1 << 22;
 constexpr int kTabLen = 64;             // score table covers sentence lengths < 64
 constexpr int kLogTabLen = 6;
 
@@ -52,6 +54,16 @@ __host__ __device__ constexpr int64_t score_slots(int64_t n, int64_t m) {
 }
 // a pair's block in a chunk, rounded up to 16 bytes (blocks start 16-byte aligned)
 __host__ __device__ constexpr int64_t score_block(int64_t n, int64_t m) { return (score_slots(n, m) + 3) & ~int64_t(3); }
+// The similarity kernels address a pair's scores with 32-bit offsets from the
+// start of its block, so a pair's block must stay below 2^31 slots (n = m =
+// 46,000 is about the largest square pair); the host rejects larger pairs.
+constexpr int64_t kMaxPairSlots = ((int64_t)1 << 31) - 4;
+// offset of score (i, c) inside its pair's block (layout: score_slots)
+__host__ __device__ inline int64_t score_pos(int i, int c, int n, int m) {
+  const int s = i >> 6, l = i & 63;
+  const int R = (n - (s << 6)) < 64 ? (n - (s << 6)) : 64;
+  return (int64_t)s * (m + 63) * 64 + (int64_t)(l + c) * R + l;
+}
 
 // One document pair of a chunk.
 struct PairDesc {
@@ -127,7 +139,15 @@ struct NwArgs {
   char *moves;          // optional: forward paths
   const int64_t *moves_off;  // [n_pairs] (local) offsets into moves
   int32_t *n_moves;     // optional [n_pairs] (global index)
+  uint64_t wait_ticks;  // limit of one bounded wait of the pipelined sweep (0: give up at once)
+  int32_t *status;      // optional: set to kStatusWaitGaveUp when a pair's sweep gives up
 };
+
+// Device status word of a call: 0, or the code of the first device failure.
+constexpr int32_t kStatusWaitGaveUp = -3;  // equals YM_EDEVICE
+// Default limit of one bounded wait (ticks of the 100 MHz constant counter):
+// far above any legitimate wait, which is at most one strip sweep.
+constexpr uint64_t kNwWaitTicks = 2000000000ull;  // 20 s
 
 // Launch wrappers (kernels.hip).
 hipError_t launch_lex_dense(const int32_t *keys, const int32_t *cnts, const int64_t *offs, const int32_t *vals, int64_t n,

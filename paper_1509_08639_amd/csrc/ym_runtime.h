@@ -66,6 +66,9 @@ size_t pair_bytes(int64_t n, int64_t m);
 LexDev lex_dev(const ym_lexicon *L);
 ym_status check_params(const ym_params *p);
 ym_status check_doc_off(const int64_t *o, int64_t n_pairs, const char *what);
+// The sizes one document pair may have: at most kMaxDocSents sentences per
+// side and fewer than 2^31 score slots (32-bit offsets inside a pair's block).
+ym_status check_pair_shape(int64_t n, int64_t m, int64_t pair);
 ym_status ensure_table(ym_ctx *c, const ym_params *p, hipStream_t st);
 // Resolve the batch's source tokens into `head` (trans_bytes(n_src_tok) bytes) and point b.trans at it.
 ym_status translate_batch(ym_ctx *c, const ym_lexicon *L, DevBatch &b, char *head, hipStream_t st);
@@ -109,6 +112,7 @@ struct ym_ctx {
                         // sentences split over spare lanes (YM_SIM_KERNEL=split), 0 bit-sliced tiles (=tile)
   int item_rows = ym::kItemRows;  // source sentences per similarity work item
   int nw_pairs_per_group = 1;     // NW workgroup size in pairs (one wave each)
+  uint64_t nw_wait_ticks = ym::kNwWaitTicks;  // limit of one bounded wait of the pipelined sweep
   // kernel timing
   bool prof = false;
   std::mutex prof_mu;

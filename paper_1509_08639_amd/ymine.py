@@ -32,7 +32,7 @@ EXPORTS = [
     "ym_nw_align", "ym_tune", "ym_mine_bidirectional", "ym_set_tuning", "ym_get_tuning", "ym_autotune",
     "ym_profile_enable", "ym_profile_read", "ym_server_start", "ym_submit", "ym_poll", "ym_server_next_done", "ym_cancel",
     "ym_server_stop",
-    "ym_server_stats", "ym_server_graph_stats",
+    "ym_server_stats", "ym_server_graph_stats", "ym_check_pair", "ym_set_wait_limit",
 ]
 
 
@@ -67,7 +67,8 @@ class DeviceBatch(C.Structure):
 
 
 class DeviceOut(C.Structure):
-    _fields_ = [("pair_off", vp), ("src_idx", vp), ("tgt_idx", vp), ("score", vp), ("align_score", vp)]
+    _fields_ = [("pair_off", vp), ("src_idx", vp), ("tgt_idx", vp), ("score", vp), ("align_score", vp),
+                ("status", vp)]
 
 
 class Tuning(C.Structure):
@@ -130,6 +131,8 @@ def lib():
     L.ym_server_stop.argtypes = [vp]
     L.ym_server_stats.argtypes = [vp, P(i64), P(i64), P(i64)]
     L.ym_server_graph_stats.argtypes = [vp, P(i64), P(i64)]
+    L.ym_check_pair.argtypes = [i64, i64]
+    L.ym_set_wait_limit.argtypes = [vp, i64]
     _lib = L
     return L
 
@@ -339,6 +342,16 @@ def mine_bidirectional(ctx: Context, lex_fwd: Lexicon, lex_rev: Lexicon, corpus,
     return _result_to_numpy(rp)
 
 
+def check_pair(n: int, m: int) -> None:
+    """Raise YmError(YM_EINVAL) if a pair of n x m sentences exceeds the library's limits (host only)."""
+    _check(lib().ym_check_pair(int(n), int(m)))
+
+
+def set_wait_limit(ctx: Context, ticks: int) -> None:
+    """Limit of one bounded wait of the pipelined NW sweep (failure injection for tests; < 0: default)."""
+    _check(lib().ym_set_wait_limit(ctx.h, int(ticks)))
+
+
 def set_tuning(ctx: Context, sim_kernel: int, item_rows: int, nw_pairs_per_group: int):
     """ym_set_tuning: similarity kernel (1 lanes, 2 lanes with split reads of
     long target sentences, 0 bit-sliced tiles), source rows per work item (64,
@@ -390,11 +403,12 @@ class DeviceMiner:
         self.src_idx = torch.zeros(max(self.cap, 1), dtype=torch.int32, device=device)
         self.tgt_idx = torch.zeros(max(self.cap, 1), dtype=torch.int32, device=device)
         self.score = torch.zeros(max(self.cap, 1), dtype=torch.float32, device=device)
+        self.status = torch.zeros(1, dtype=torch.int32, device=device)
         self.b = DeviceBatch(self.n_pairs, _ptr(self.sdo, i64), _ptr(self.tdo, i64), self.d_ssent.data_ptr(),
                              self.d_stok.data_ptr(), self.d_tsent.data_ptr(), self.d_ttok.data_ptr(),
                              int(corpus.src_tok.shape[0]), int(corpus.tgt_tok.shape[0]))
         self.o = DeviceOut(self.pair_off.data_ptr(), self.src_idx.data_ptr(), self.tgt_idx.data_ptr(),
-                           self.score.data_ptr(), self.align.data_ptr())
+                           self.score.data_ptr(), self.align.data_ptr(), self.status.data_ptr())
 
     def run(self, w, gap, threshold, stream=None):
         """Enqueue one mining pass on `stream` (default: torch's current stream)."""
@@ -404,7 +418,11 @@ class DeviceMiner:
                                     self.ws_bytes, C.byref(self.o), vp(st)))
 
     def result(self) -> dict:
+        """The last pass's result; raises YmError(YM_EDEVICE) if a pair could not be completed."""
         self.torch.cuda.synchronize()
+        st = int(self.status.cpu().item())
+        if st != 0:
+            raise YmError(st, "a pair's pipelined Needleman-Wunsch sweep gave up on a bounded wait")
         po = self.pair_off.cpu().numpy()
         k = int(po[-1])
         return dict(pair_off=po, src_idx=self.src_idx[:k].cpu().numpy(), tgt_idx=self.tgt_idx[:k].cpu().numpy(),

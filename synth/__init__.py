@@ -28,7 +28,7 @@ def build(force: bool = True) -> str:
     """Compile libsynth.so next to its source."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", _SRC, "-o", tmp, "-lm"])
+        subprocess.check_call(["gcc", "-O2", "-std=gnu99", "-pthread", "-fPIC", "-shared", _SRC, "-o", tmp, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -99,6 +99,11 @@ def _load():
             C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(_Corpus),
         ]
         lib.synth_free.argtypes = [C.POINTER(_Corpus)]
+        lib.synth_generate_mt.argtypes = [
+            C.POINTER(_Cfg), C.c_uint64, C.POINTER(C.c_int64), C.c_int64,
+            C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int,
+            C.POINTER(C.c_void_p), C.POINTER(C.c_int64)]
+        lib.synth_collect.argtypes = [C.c_void_p] + [C.c_void_p] * 9
         lib.synth_make_lexicon.argtypes = [
             C.c_int32, C.c_int64, C.c_int32, C.c_int32, C.c_int64, C.c_uint64, C.POINTER(_Lex)]
         lib.synth_free_lexicon.argtypes = [C.POINTER(_Lex)]
@@ -327,39 +332,37 @@ def uniform_ints(seed: int, stream: int, n: int, lo: int, hi: int) -> np.ndarray
     return out
 
 
-def generate(cfg: Config, lex: Lexicon, pair_ids=None, seed: int | None = None) -> Corpus:
-    """Documents for the listed pair ids (default: 0..cfg.n_pairs-1)."""
+def generate(cfg: Config, lex: Lexicon, pair_ids=None, seed: int | None = None, threads: int | None = None) -> Corpus:
+    """Documents for the listed pair ids (default: 0..cfg.n_pairs-1), drawn by
+    `threads` worker threads (default: the CPUs this process may use, at most
+    16); the result does not depend on the thread count."""
     lib = _load()
     if pair_ids is None:
         pair_ids = np.arange(cfg.n_pairs, dtype=np.int64)
     pair_ids = np.ascontiguousarray(pair_ids, dtype=np.int64)
+    if threads is None:
+        threads = min(16, len(os.sched_getaffinity(0)))
     first, count = lex.dense(cfg.vocab)
     tgt = np.ascontiguousarray(lex.tgt_ids if lex.tgt_ids.size else np.zeros(1, np.int32))
     c = cfg._c()
-    out = _Corpus()
-    rc = lib.synth_generate(C.byref(c), cfg.seed if seed is None else seed,
-                            _ptr(pair_ids, C.c_int64), pair_ids.shape[0],
-                            _ptr(first, C.c_int64), _ptr(count, C.c_int32), _ptr(tgt, C.c_int32),
-                            C.byref(out))
+    job = C.c_void_p()
+    tot = (C.c_int64 * 5)()
+    rc = lib.synth_generate_mt(C.byref(c), cfg.seed if seed is None else seed,
+                               _ptr(pair_ids, C.c_int64), pair_ids.shape[0],
+                               _ptr(first, C.c_int64), _ptr(count, C.c_int32), _ptr(tgt, C.c_int32),
+                               int(threads), C.byref(job), tot)
     if rc != 0:
-        raise RuntimeError(f"synth_generate failed ({rc})")
-
-    def arr(p, n, dt):
-        if n == 0:
-            return np.zeros(0, dtype=dt)
-        return np.ctypeslib.as_array(p, shape=(n,)).copy()
-    try:
-        np_ = out.n_pairs
-        corpus = Corpus(
-            arr(out.src_doc_off, np_ + 1, np.int64), arr(out.src_sent_off, out.n_src_sent + 1, np.int64),
-            arr(out.src_tok, out.n_src_tok, np.int32),
-            arr(out.tgt_doc_off, np_ + 1, np.int64), arr(out.tgt_sent_off, out.n_tgt_sent + 1, np.int64),
-            arr(out.tgt_tok, out.n_tgt_tok, np.int32),
-            arr(out.truth_off, np_ + 1, np.int64), arr(out.truth_src, out.n_truth, np.int32),
-            arr(out.truth_tgt, out.n_truth, np.int32), pair_ids.copy())
-    finally:
-        lib.synth_free(C.byref(out))
-    return corpus
+        raise RuntimeError(f"synth_generate_mt failed ({rc})")
+    P = pair_ids.shape[0]
+    ns, nt, nts, ntt, ntr = (int(x) for x in tot)
+    out = [np.empty(P + 1, np.int64), np.empty(ns + 1, np.int64), np.empty(max(nts, 1), np.int32),
+           np.empty(P + 1, np.int64), np.empty(nt + 1, np.int64), np.empty(max(ntt, 1), np.int32),
+           np.empty(P + 1, np.int64), np.empty(max(ntr, 1), np.int32), np.empty(max(ntr, 1), np.int32)]
+    rc = lib.synth_collect(job, *[a.ctypes.data_as(C.c_void_p) for a in out])
+    if rc != 0:
+        raise RuntimeError(f"synth_collect failed ({rc})")
+    return Corpus(out[0], out[1], out[2][:nts], out[3], out[4], out[5][:ntt], out[6], out[7][:ntr], out[8][:ntr],
+                  pair_ids.copy())
 
 
 def config(k: int, **over) -> Config:

@@ -26,6 +26,7 @@
  *     interleaved at random positions among independent target sentences.
  */
 #include <math.h>
+#include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -75,7 +76,9 @@ static inline double rng_normal(rng_t *r) {
 typedef struct {
   int32_t V;
   double s;
-  double *cdf; /* cdf[r-1] = P(rank <= r) */
+  double *cdf;     /* cdf[r-1] = P(rank <= r) */
+  int32_t *guide;  /* guide[k]: smallest index with cdf > k / G (G a power of two) */
+  int32_t lg;      /* G = 2^lg */
 } zipf_t;
 
 static int zipf_init(zipf_t *z, int32_t V, double s) {
@@ -90,20 +93,39 @@ static int zipf_init(zipf_t *z, int32_t V, double s) {
   }
   for (int32_t r = 0; r < V; r++) z->cdf[r] /= acc;
   z->cdf[V - 1] = 1.0;
+  /* guide table of the inverse CDF (about four buckets per rank, at most 2^22) */
+  z->lg = 10;
+  while (z->lg < 22 && ((int64_t)1 << z->lg) < 4 * (int64_t)V) z->lg++;
+  const int64_t G = (int64_t)1 << z->lg;
+  z->guide = (int32_t *)malloc(sizeof(int32_t) * (size_t)G);
+  if (!z->guide) {
+    free(z->cdf);
+    return -1;
+  }
+  int32_t r = 0;
+  for (int64_t k = 0; k < G; k++) {
+    const double t = (double)k / (double)G; /* exact: G is a power of two */
+    while (r < V - 1 && z->cdf[r] <= t) r++;
+    z->guide[k] = r;
+  }
   return 0;
 }
 
+static void zipf_free(zipf_t *z) {
+  free(z->cdf);
+  free(z->guide);
+  z->cdf = NULL;
+  z->guide = NULL;
+}
+
+/* The smallest index r with cdf[r] > u (inverse-CDF sampling).  u * G is
+ * exact, so every index below guide[floor(u G)] has cdf <= floor(u G) / G <= u
+ * and the scan from there finds the same index as a binary search would. */
 static inline int32_t zipf_draw(const zipf_t *z, rng_t *r) {
-  double u = rng_unif(r);
-  int32_t lo = 0, hi = z->V - 1; /* smallest index with cdf > u */
-  while (lo < hi) {
-    int32_t mid = lo + (hi - lo) / 2;
-    if (z->cdf[mid] > u)
-      hi = mid;
-    else
-      lo = mid + 1;
-  }
-  return lo;
+  const double u = rng_unif(r);
+  int32_t k = z->guide[(int64_t)(u * (double)((int64_t)1 << z->lg))];
+  while (k < z->V - 1 && z->cdf[k] <= u) k++;
+  return k;
 }
 
 /* ------------------------------------------------------------ config */
@@ -225,13 +247,11 @@ int synth_free(synth_corpus *o) {
  * exactly by listing its ids.
  * Lexicon is CSR over source ids: lex_first/lex_count indexed by id < V.
  */
-int synth_generate(const synth_cfg *c, uint64_t seed, const int64_t *pair_ids, int64_t n_pairs,
-                   const int64_t *lex_first, const int32_t *lex_count, const int32_t *lex_tgt,
-                   synth_corpus *out) {
+static int generate_serial(const synth_cfg *c, const zipf_t *zp, uint64_t seed, const int64_t *pair_ids,
+                           int64_t n_pairs, const int64_t *lex_first, const int32_t *lex_count,
+                           const int32_t *lex_tgt, synth_corpus *out) {
   memset(out, 0, sizeof(*out));
-  zipf_t z;
-  if (c->vocab <= 0 || c->len_min < 0 || c->len_max < c->len_min) return -2;
-  if (zipf_init(&z, c->vocab, c->zipf_s)) return -1;
+  const zipf_t z = *zp;
   lexview lx = {lex_first, lex_count, lex_tgt};
 
   vec64 sdoc = {0}, tdoc = {0}, ssent = {0}, tsent = {0}, toff = {0};
@@ -422,7 +442,6 @@ int synth_generate(const synth_cfg *c, uint64_t seed, const int64_t *pair_ids, i
   out->truth_src = trs.p;
   out->truth_tgt = trt.p;
   out->n_truth = trs.n;
-  free(z.cdf);
   free(pick);
   free(order);
   free(place);
@@ -435,7 +454,6 @@ int synth_generate(const synth_cfg *c, uint64_t seed, const int64_t *pair_ids, i
   return 0;
 
 fail:
-  free(z.cdf);
   free(pick);
   free(order);
   free(place);
@@ -456,6 +474,188 @@ fail:
   free(trt.p);
   memset(out, 0, sizeof(*out));
   return -1;
+}
+
+int synth_generate(const synth_cfg *c, uint64_t seed, const int64_t *pair_ids, int64_t n_pairs,
+                   const int64_t *lex_first, const int32_t *lex_count, const int32_t *lex_tgt,
+                   synth_corpus *out) {
+  memset(out, 0, sizeof(*out));
+  zipf_t z;
+  if (c->vocab <= 0 || c->len_min < 0 || c->len_max < c->len_min) return -2;
+  if (zipf_init(&z, c->vocab, c->zipf_s)) return -1;
+  const int rc = generate_serial(c, &z, seed, pair_ids, n_pairs, lex_first, lex_count, lex_tgt, out);
+  zipf_free(&z);
+  return rc;
+}
+
+/*
+ * The same corpus generated by several threads, each over a contiguous range
+ * of the listed pairs (every pair depends only on its own id, so the result is
+ * identical).  synth_generate_mt leaves the parts in a job and reports the
+ * totals; the caller allocates the output arrays and synth_collect copies the
+ * parts into them (rebasing offsets) and releases the job.
+ */
+typedef struct {
+  const synth_cfg *c;
+  const zipf_t *z;
+  uint64_t seed;
+  const int64_t *ids;
+  int64_t n;
+  const int64_t *first;
+  const int32_t *count;
+  const int32_t *tgt;
+  synth_corpus out;
+  int rc;
+} gen_part;
+
+typedef struct {
+  int n_parts;
+  gen_part *parts;
+} synth_job;
+
+static void *gen_part_run(void *arg) {
+  gen_part *g = (gen_part *)arg;
+  g->rc = generate_serial(g->c, g->z, g->seed, g->ids, g->n, g->first, g->count, g->tgt, &g->out);
+  return NULL;
+}
+
+static void job_free(synth_job *j) {
+  if (!j) return;
+  for (int k = 0; k < j->n_parts; k++) synth_free(&j->parts[k].out);
+  free(j->parts);
+  free(j);
+}
+
+/* totals[0..4]: source sentences, target sentences, source tokens, target
+ * tokens, planted pairs */
+int synth_generate_mt(const synth_cfg *c, uint64_t seed, const int64_t *pair_ids, int64_t n_pairs,
+                      const int64_t *lex_first, const int32_t *lex_count, const int32_t *lex_tgt, int threads,
+                      void **job_out, int64_t totals[5]) {
+  *job_out = NULL;
+  if (c->vocab <= 0 || c->len_min < 0 || c->len_max < c->len_min) return -2;
+  zipf_t z;
+  if (zipf_init(&z, c->vocab, c->zipf_s)) return -1;
+  int T = threads < 1 ? 1 : threads;
+  if ((int64_t)T > n_pairs / 16) T = n_pairs / 16 > 0 ? (int)(n_pairs / 16) : 1;
+  synth_job *j = (synth_job *)calloc(1, sizeof(synth_job));
+  gen_part *parts = j ? (gen_part *)calloc((size_t)T, sizeof(gen_part)) : NULL;
+  pthread_t *th = (pthread_t *)calloc((size_t)T, sizeof(pthread_t));
+  if (!j || !parts || !th) {
+    free(j);
+    free(parts);
+    free(th);
+    zipf_free(&z);
+    return -1;
+  }
+  j->n_parts = T;
+  j->parts = parts;
+  int rc = 0;
+  for (int k = 0; k < T; k++) {
+    const int64_t p0 = n_pairs * k / T, p1 = n_pairs * (k + 1) / T;
+    gen_part g = {c, &z, seed, pair_ids + p0, p1 - p0, lex_first, lex_count, lex_tgt, {0}, 0};
+    parts[k] = g;
+  }
+  int started = 0;
+  for (int k = 1; k < T; k++) {
+    if (pthread_create(&th[k], NULL, gen_part_run, &parts[k]) != 0) {
+      gen_part_run(&parts[k]);
+      th[k] = 0;
+    } else {
+      started |= 1;
+    }
+  }
+  gen_part_run(&parts[0]);
+  for (int k = 1; k < T; k++)
+    if (th[k]) pthread_join(th[k], NULL);
+  (void)started;
+  free(th);
+  zipf_free(&z);
+  for (int k = 0; k < T; k++) rc |= parts[k].rc;
+  if (rc) {
+    job_free(j);
+    return -1;
+  }
+  for (int q = 0; q < 5; q++) totals[q] = 0;
+  for (int k = 0; k < T; k++) {
+    totals[0] += parts[k].out.n_src_sent;
+    totals[1] += parts[k].out.n_tgt_sent;
+    totals[2] += parts[k].out.n_src_tok;
+    totals[3] += parts[k].out.n_tgt_tok;
+    totals[4] += parts[k].out.n_truth;
+  }
+  *job_out = j;
+  return 0;
+}
+
+typedef struct {
+  const synth_corpus *in;
+  int64_t pair0, ssent0, tsent0, stok0, ttok0, truth0;
+  int64_t *sdoc, *ssent, *tdoc, *tsent, *toff;
+  int32_t *stok, *ttok, *trs, *trt;
+} collect_part;
+
+static void *collect_run(void *arg) {
+  collect_part *q = (collect_part *)arg;
+  const synth_corpus *o = q->in;
+  for (int64_t p = 1; p <= o->n_pairs; p++) {
+    q->sdoc[q->pair0 + p] = q->ssent0 + o->src_doc_off[p];
+    q->tdoc[q->pair0 + p] = q->tsent0 + o->tgt_doc_off[p];
+    q->toff[q->pair0 + p] = q->truth0 + o->truth_off[p];
+  }
+  for (int64_t s = 1; s <= o->n_src_sent; s++) q->ssent[q->ssent0 + s] = q->stok0 + o->src_sent_off[s];
+  for (int64_t s = 1; s <= o->n_tgt_sent; s++) q->tsent[q->tsent0 + s] = q->ttok0 + o->tgt_sent_off[s];
+  if (o->n_src_tok) memcpy(q->stok + q->stok0, o->src_tok, sizeof(int32_t) * (size_t)o->n_src_tok);
+  if (o->n_tgt_tok) memcpy(q->ttok + q->ttok0, o->tgt_tok, sizeof(int32_t) * (size_t)o->n_tgt_tok);
+  if (o->n_truth) {
+    memcpy(q->trs + q->truth0, o->truth_src, sizeof(int32_t) * (size_t)o->n_truth);
+    memcpy(q->trt + q->truth0, o->truth_tgt, sizeof(int32_t) * (size_t)o->n_truth);
+  }
+  return NULL;
+}
+
+/* Copy a job's parts into the caller's arrays (sizes from the totals;
+ * offsets arrays hold n+1 entries) and release the job. */
+int synth_collect(void *job, int64_t *src_doc_off, int64_t *src_sent_off, int32_t *src_tok, int64_t *tgt_doc_off,
+                  int64_t *tgt_sent_off, int32_t *tgt_tok, int64_t *truth_off, int32_t *truth_src,
+                  int32_t *truth_tgt) {
+  synth_job *j = (synth_job *)job;
+  if (!j) return -1;
+  const int T = j->n_parts;
+  collect_part *cp = (collect_part *)calloc((size_t)T, sizeof(collect_part));
+  pthread_t *th = (pthread_t *)calloc((size_t)T, sizeof(pthread_t));
+  if (!cp || !th) {
+    free(cp);
+    free(th);
+    job_free(j);
+    return -1;
+  }
+  src_doc_off[0] = tgt_doc_off[0] = truth_off[0] = 0;
+  src_sent_off[0] = tgt_sent_off[0] = 0;
+  int64_t b[6] = {0, 0, 0, 0, 0, 0};
+  for (int k = 0; k < T; k++) {
+    const synth_corpus *o = &j->parts[k].out;
+    collect_part x = {o, b[0], b[1], b[2], b[3], b[4], b[5], src_doc_off, src_sent_off, tgt_doc_off, tgt_sent_off,
+                      truth_off, src_tok, tgt_tok, truth_src, truth_tgt};
+    cp[k] = x;
+    b[0] += o->n_pairs;
+    b[1] += o->n_src_sent;
+    b[2] += o->n_tgt_sent;
+    b[3] += o->n_src_tok;
+    b[4] += o->n_tgt_tok;
+    b[5] += o->n_truth;
+  }
+  for (int k = 1; k < T; k++)
+    if (pthread_create(&th[k], NULL, collect_run, &cp[k]) != 0) {
+      collect_run(&cp[k]);
+      th[k] = 0;
+    }
+  collect_run(&cp[0]);
+  for (int k = 1; k < T; k++)
+    if (th[k]) pthread_join(th[k], NULL);
+  free(cp);
+  free(th);
+  job_free(j);
+  return 0;
 }
 
 /*

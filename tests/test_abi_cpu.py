@@ -56,3 +56,16 @@ def test_no_oracle_in_product():
             if f.endswith((".py", ".hip", ".h", ".cpp")):
                 t = open(os.path.join(dp, f)).read()
                 assert "oracle" not in t.lower(), f
+
+
+def test_pair_size_limits_on_the_host(lib):
+    """Pairs whose score block would need 32-bit offsets of 2^31 or more (the
+    similarity kernels' addressing) or documents of more than 2^22 sentences
+    are rejected before any device work; the check needs no device."""
+    lib.check_pair(0, 0)
+    lib.check_pair(40000, 40000)  # about 1.6e9 score slots
+    lib.check_pair(1 << 22, 100)
+    for n, m in [(50000, 50000), (46341, 46341), ((1 << 22) + 1, 1), (1, (1 << 22) + 1), (-1, 5)]:
+        with pytest.raises(lib.YmError) as e:
+            lib.check_pair(n, m)
+        assert e.value.code == lib.YM_EINVAL, (n, m)

@@ -179,8 +179,7 @@ def test_mine_end_to_end_batch_sample(ym, ctx, O):
     want = O.mine(OL, c, w, -0.2, 0.5)
     S, _, _ = ym.similarity(ctx, L, c, w)
     ties = parity.compare_mined(O, OL, c, w, F32(-0.2), F32(0.5), got, want, S)
-    assert len(ties) <= 2, ties
-    print("admissible ties:", ties)
+    parity.assert_ties("batch_10k_every_50th", ties)
 
 
 def test_device_and_per_pair_forms_match(ym, ctx, O):
@@ -226,7 +225,7 @@ def test_mine_ragged_edges_end_to_end(ym, ctx, O):
     want = O.mine(OL, c, w, -0.2, 0.5)
     S, _, _ = ym.similarity(ctx, L, c, w)
     ties = parity.compare_mined(O, OL, c, w, F32(-0.2), F32(0.5), got, want, S)
-    assert len(ties) <= 1, ties
+    parity.assert_ties("ragged_30_pairs_seed4", ties)
 
 
 def test_long_pair(ym, ctx, O):
@@ -240,7 +239,7 @@ def test_long_pair(ym, ctx, O):
     want = O.mine(OL, c, w, -0.2, 0.5)
     S, _, _ = ym.similarity(ctx, L, c, w)
     ties = parity.compare_mined(O, OL, c, w, F32(-0.2), F32(0.5), got, want, S)
-    assert len(ties) <= 1, ties
+    parity.assert_ties("long_64x2000x2200_pair7", ties)
 
 
 def test_full_batch_sampled(ym, ctx, O):
@@ -265,10 +264,10 @@ def test_full_batch_sampled(ym, ctx, O):
     sub = c.subset(sample)
     OL = O.lexicon(lex.src_ids, lex.off, lex.tgt_ids)
     want = O.mine(OL, sub, w, -0.2, 0.5)
-    for k, p in enumerate(sample):
-        gp, gs = parity.pairs_of(got, int(p))
-        wp, ws = parity.pairs_of(want, k)
-        assert gp == wp and np.max(np.abs(gs - ws), initial=0) <= parity.TOL_S, int(p)
+    got_sub = parity.select_pairs(got, sample)
+    S, _, _ = ym.similarity(ctx, L, sub, w)
+    ties = parity.compare_mined(O, OL, sub, w, F32(-0.2), F32(0.5), got_sub, want, S)
+    parity.assert_ties("batch_10k_full_sample25", ties)
     # a second run gives the same bits
     dm.run(w, -0.2, 0.5)
     again = dm.result()
@@ -348,6 +347,107 @@ def test_scale_workload_sample(ym, ctx, ctx_split, O, split):
     want = O.mine(OL, c, w, F32(-0.2), F32(0.5))
     S, _, _ = ym.similarity(ctx, L, c, w)
     ties = parity.compare_mined(O, OL, c, w, F32(-0.2), F32(0.5), got, want, S)
-    assert len(ties) <= 2, ties
+    parity.assert_ties("scale_1M_every_20000th", ties)
     lens = np.diff(c.src_sent_off)
     assert lens.max() > 31  # the long-row path is exercised
+
+
+def test_single_pair_end_to_end(ym, ctx, O):
+    """The single 40 x 45 pair (vocabulary 5k, 4,000 translated ids, 60%
+    planted) through every entry point, against the oracle."""
+    cfg = synth.CONFIGS[0]
+    lex = synth.make_lexicon(cfg)
+    c = synth.generate(cfg, lex)
+    w = synth.weights(cfg.seed)
+    L = ctx.lexicon(lex.src_ids, lex.off, lex.tgt_ids)
+    OL = O.lexicon(lex.src_ids, lex.off, lex.tgt_ids)
+    want = O.mine(OL, c, w, F32(-0.2), F32(0.5))
+    S, _, _ = ym.similarity(ctx, L, c, w)
+    got = ym.mine(ctx, L, c, w, -0.2, 0.5)
+    parity.assert_ties("single_40x45", parity.compare_mined(O, OL, c, w, F32(-0.2), F32(0.5), got, want, S))
+    assert int(got["pair_off"][-1]) > 0
+    dm = ym.DeviceMiner(ctx, L, c)
+    dm.run(w, -0.2, 0.5)
+    for r in (ym.mine_per_pair(ctx, L, c, w, -0.2, 0.5), dm.result()):
+        parity.compare_result_fields(r, got, "single pair: forms differ")
+
+
+def test_served_tail_pair_4000x4000(ym, ctx, O):
+    """The largest request of the served stream (4,000 x 4,000 sentences,
+    vocabulary 200k, 1M lexicon pairs), through the batch entry point and the
+    server, against the oracle (scores computed in row bands)."""
+    cfg = synth.config(3, count_kind=0, n_fixed=4000, m_fixed=4000, n_pairs=1)
+    lex = synth.make_lexicon(cfg)
+    c = synth.generate(cfg, lex)
+    w = synth.weights(cfg.seed)
+    L = ctx.lexicon(lex.src_ids, lex.off, lex.tgt_ids)
+    OL = O.lexicon(lex.src_ids, lex.off, lex.tgt_ids)
+    src, tgt = c.pair(0)
+    want, So = parity.oracle_pair_banded(O, OL, src, tgt, w, F32(-0.2), F32(0.5))
+    got = ym.mine(ctx, L, c, w, -0.2, 0.5)
+    if not (np.array_equal(got["src_idx"], want["src_idx"]) and np.array_equal(got["tgt_idx"], want["tgt_idx"])
+            and got["align_score"].tobytes() == want["align_score"].tobytes()):
+        S, _, _ = ym.similarity(ctx, L, c, w)
+        assert np.max(np.abs(S - So.reshape(-1))) <= parity.TOL_S
+        h, mv, _ = O.nw(S.reshape(4000, 4000), F32(-0.2))
+        si, ti, _ = O.emit(S.reshape(4000, 4000), mv, F32(0.5))
+        tie = [(0, np.argwhere(S.reshape(4000, 4000) != So).tolist())]
+        assert np.array_equal(si, got["src_idx"]) and np.array_equal(ti, got["tgt_idx"]) and h == got["align_score"][0]
+        parity.assert_ties("served_tail_4000x4000", tie)
+    else:
+        parity.compare_result_fields(got, want, "4000 x 4000")
+        parity.assert_ties("served_tail_4000x4000", [])
+    srv = ym.Server(ctx, L, w, -0.2, 0.5, max_pairs_per_step=8, use_graph=1)
+    try:
+        r = srv.poll(srv.submit(c))
+    finally:
+        srv.stop()
+    parity.compare_result_fields(r, got, "served 4000 x 4000")
+
+
+def test_pipelined_sweep_give_up_is_an_error(ym, O):
+    """A bounded wait of the pipelined sweep that gives up (forced from the
+    host: a zero wait limit makes every such wait give up at once, and every
+    kernel still runs to its end) fails the call with YM_EDEVICE; pairs that
+    do not need the pipelined sweep are not affected, and the default limit
+    restores normal results."""
+    ctx = ym.Context(0)
+    r = np.random.default_rng(31)
+    big = [r.random((700, 90)).astype(np.float32)]
+    small = [r.random((60, 70)).astype(np.float32)]
+    ym.set_wait_limit(ctx, 0)
+    with pytest.raises(ym.YmError) as e:
+        ym.nw_align(ctx, big + small, -0.2, 0.5)
+    assert e.value.code == ym.YM_EDEVICE
+    align, moves, res = ym.nw_align(ctx, small, -0.2, 0.5)
+    assert align[0].tobytes() == O.nw(small[0], F32(-0.2))[0].tobytes()
+    lex = parity.random_lexicon(3)
+    c = parity.random_corpus(3, n_pairs=3, nmax=40, mmax=40, lmax_src=20, lmax_tgt=20)
+    big_pair = synth.from_lists([[np.array([1, 2, 3], np.int32)] * 500], [[np.array([2, 3], np.int32)] * 60])
+    w = np.array([-1.5, 3.0, 2.0, 0.5], np.float32)
+    L = ctx.lexicon(lex.src_ids, lex.off, lex.tgt_ids)
+    with pytest.raises(ym.YmError) as e:
+        ym.mine(ctx, L, big_pair, w, -0.2, 0.5)
+    assert e.value.code == ym.YM_EDEVICE
+    dm = ym.DeviceMiner(ctx, L, big_pair)
+    dm.run(w, -0.2, 0.5)
+    with pytest.raises(ym.YmError) as e:
+        dm.result()
+    assert e.value.code == ym.YM_EDEVICE
+    srv = ym.Server(ctx, L, w, -0.2, 0.5, max_pairs_per_step=4)
+    try:
+        t_small = srv.submit(c.subset([0]))
+        t_big = srv.submit(big_pair)
+        t_small2 = srv.submit(c.subset([1]))
+        with pytest.raises(ym.YmError) as e:
+            srv.poll(t_big)
+        assert e.value.code == ym.YM_EDEVICE
+        assert srv.poll(t_small) is not None and srv.poll(t_small2) is not None
+    finally:
+        srv.stop()
+    ym.set_wait_limit(ctx, -1)
+    got = ym.mine(ctx, L, big_pair, w, -0.2, 0.5)
+    OL = O.lexicon(lex.src_ids, lex.off, lex.tgt_ids)
+    parity.compare_result_fields(got, O.mine(OL, big_pair, w, F32(-0.2), F32(0.5)), "after the limit is restored")
+    dm.run(w, -0.2, 0.5)
+    parity.compare_result_fields(dm.result(), got, "device form after the limit is restored")

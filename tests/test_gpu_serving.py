@@ -11,6 +11,8 @@ import pytest
 import oracle
 import synth
 
+from . import parity
+
 pytestmark = pytest.mark.gpu
 
 
@@ -80,8 +82,7 @@ def test_alone_equals_in_mix_and_batch(ym, setup):
     O = oracle.default()
     want = O.mine(O.lexicon(lex.src_ids, lex.off, lex.tgt_ids), corpus.subset(probe), w, -0.2, 0.5)
     for k, p in enumerate(probe):
-        a, b = want["pair_off"][k], want["pair_off"][k + 1]
-        assert np.array_equal(alone[p]["src_idx"], want["src_idx"][a:b])
+        parity.compare_result_fields(alone[p], parity.select_pairs(want, [k]), f"probe {p}")
 
 
 def test_budget_admission(ym, setup):

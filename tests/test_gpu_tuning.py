@@ -44,11 +44,17 @@ def test_every_configuration_gives_the_same_result(ym):
     S_ref, ms_ref, mt_ref = ym.similarity(ctx, L, c, w)
     OL = oracle.default().lexicon(lex.src_ids, lex.off, lex.tgt_ids)
     want = oracle.default().mine(OL, c, w, F32(-0.2), F32(0.5))
-    parity.compare_mined(oracle.default(), OL, c, w, F32(-0.2), F32(0.5), ref, want, S_ref)
+    ties = parity.compare_mined(oracle.default(), OL, c, w, F32(-0.2), F32(0.5), ref, want, S_ref)
+    parity.assert_ties("tuning_random_24_seed21", ties)
+    # the device form with the workspace the library asks for (the whole batch
+    # as one chunk), which must hold every launch configuration's plan
+    dm = ym.DeviceMiner(ctx, L, c)
     for sk, rows, ppg in CONFIGS:
         ym.set_tuning(ctx, sk, rows, ppg)
         assert ym.get_tuning(ctx) == dict(sim_kernel=sk, item_rows=rows, nw_pairs_per_group=ppg)
         _same(ref, ym.mine(ctx, L, c, w, -0.2, 0.5))
+        dm.run(w, -0.2, 0.5)
+        _same(ref, dm.result())
         S, ms, mt = ym.similarity(ctx, L, c, w)
         assert np.array_equal(S, S_ref) and np.array_equal(ms, ms_ref) and np.array_equal(mt, mt_ref), (sk, rows)
 
