@@ -102,31 +102,39 @@ def timed_passes(torch, ctx, dm, w, gap, tau, steps, warmup):
     t1 = time.perf_counter()
     prof = ctx.profile_read()
     ctx.profile(False)
-    kern = {k: dict(avg_ms=ms / max(n, 1), launches=n) for k, (ms, n) in prof.items()}
+    kern = {k: dict(avg_ms=ms / max(n, 1), launches=n, launches_per_step=n / steps, ms_per_step=ms / steps)
+            for k, (ms, n) in prof.items()}
     return (t1 - t0) / steps, kern
 
 
 def roofline(kern, st, name):
-    """Roofline figures of the dominant kernel (per launch: algorithmic work of
-    the whole pass / that kernel's average duration)."""
+    """Roofline figures of the dominant kernel.  A pass may launch a kernel
+    more than once (one launch per workspace chunk), so the algorithmic work of
+    one launch is the pass's work divided by the launches per pass, and the
+    achieved rate is that over the kernel's average launch duration (equal to
+    the pass's work over the kernel's summed time per pass)."""
     cells = st["cells"]
     sim_ops_per_cell = st["mean_b"] + st["mean_ka"] + 20.0
     sim_ops = sim_ops_per_cell * cells
     nw_bytes = 4.25 * cells
-    sim_ms, nw_ms = kern["similarity"]["avg_ms"], kern["nw"]["avg_ms"]
-    kern["similarity"].update(bound="alu", algorithmic_ops=sim_ops,
-                              achieved_TOPs=sim_ops / (sim_ms * 1e-3) / 1e12 if sim_ms else None)
-    kern["nw"].update(bound="hbm", algorithmic_bytes=nw_bytes,
-                      achieved_GBs=nw_bytes / (nw_ms * 1e-3) / 1e9 if nw_ms else None,
-                      gcups=cells / (nw_ms * 1e-3) / 1e9 if nw_ms else None)
-    if sim_ms >= nw_ms:
-        ach = kern["similarity"]["achieved_TOPs"]
+    sim, nw = kern["similarity"], kern["nw"]
+    sim_ops_launch = sim_ops / max(sim["launches_per_step"], 1e-9)
+    nw_bytes_launch = nw_bytes / max(nw["launches_per_step"], 1e-9)
+    sim.update(bound="alu", algorithmic_ops_per_launch=sim_ops_launch,
+               achieved_TOPs=sim_ops_launch / (sim["avg_ms"] * 1e-3) / 1e12 if sim["avg_ms"] else None)
+    nw.update(bound="hbm", algorithmic_bytes_per_launch=nw_bytes_launch,
+              achieved_GBs=nw_bytes_launch / (nw["avg_ms"] * 1e-3) / 1e9 if nw["avg_ms"] else None,
+              gcups=cells / (nw["ms_per_step"] * 1e-3) / 1e9 if nw["ms_per_step"] else None)
+    if sim["ms_per_step"] >= nw["ms_per_step"]:
+        ach = sim["achieved_TOPs"]
         return dict(kernel="similarity", bound="alu", achieved=ach, peak=ALU_PEAK_TOPS, unit="TOP/s",
                     frac=ach / ALU_PEAK_TOPS, traffic=profiled_traffic("sim_kernel", name),
-                    per_unit=f"{sim_ops_per_cell:.2f} ops/cell (mean b + mean k*a + 20) x {cells} cells")
-    ach = kern["nw"]["achieved_GBs"]
+                    per_unit=f"{sim_ops_per_cell:.2f} ops/cell (mean b + mean k*a + 20) x {cells} cells per pass, "
+                             f"{sim['launches_per_step']:g} launches per pass")
+    ach = nw["achieved_GBs"]
     return dict(kernel="nw", bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
-                traffic=profiled_traffic("nw_kernel", name), per_unit=f"4.25 B/cell x {cells} cells")
+                traffic=profiled_traffic("nw_kernel", name),
+                per_unit=f"4.25 B/cell x {cells} cells per pass, {nw['launches_per_step']:g} launches per pass")
 
 
 def compare(got, want, pairs_got):

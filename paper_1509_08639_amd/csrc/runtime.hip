@@ -180,6 +180,42 @@ ym_status Chunk::layout(const int64_t *sdo, const int64_t *tdo, int64_t p0_, int
   return YM_OK;
 }
 
+// Indices 0..n-1 ordered by key, largest first, equal keys in index order: a
+// stable least-significant-digit radix sort (8-bit digits, a pass skipped when
+// every key has the same digit).  Launch order only; results never depend on it.
+static void order_desc(const uint32_t *key, int64_t n, int32_t *out) {
+  std::vector<int32_t> tmp((size_t)n);
+  std::vector<uint32_t> k0((size_t)n), k1((size_t)n);
+  for (int64_t q = 0; q < n; q++) {
+    out[q] = (int32_t)q;
+    k0[q] = ~key[q];  // ascending on the complement = descending on the key
+  }
+  int32_t *a = out, *b = tmp.data();
+  uint32_t *ka = k0.data(), *kb = k1.data();
+  for (int shift = 0; shift < 32; shift += 8) {
+    int64_t cnt[256] = {0};
+    for (int64_t q = 0; q < n; q++) cnt[(ka[q] >> shift) & 255]++;
+    bool one = false;
+    for (int d = 0; d < 256; d++) one |= cnt[d] == n;
+    if (one) continue;
+    int64_t pos[256], acc = 0;
+    for (int d = 0; d < 256; d++) {
+      pos[d] = acc;
+      acc += cnt[d];
+    }
+    for (int64_t q = 0; q < n; q++) {
+      const int64_t at = pos[(ka[q] >> shift) & 255]++;
+      b[at] = a[q];
+      kb[at] = ka[q];
+    }
+    std::swap(a, b);
+    std::swap(ka, kb);
+  }
+  if (a != out) std::memcpy(out, a, (size_t)n * sizeof(int32_t));
+}
+
+static inline uint32_t clamp_key(int64_t v) { return v > (int64_t)0xffffffffLL ? 0xffffffffu : (uint32_t)v; }
+
 // Fill descriptors / items / move offsets into pinned host memory.
 void Chunk::fill_host(const int64_t *sdo, const int64_t *tdo, char *host) const {
   PairDesc *descs = (PairDesc *)(host + off_descs);
@@ -188,6 +224,8 @@ void Chunk::fill_host(const int64_t *sdo, const int64_t *tdo, char *host) const 
   int32_t *big = (int32_t *)(host + off_big);
   int32_t *order = (int32_t *)(host + off_order);
   int64_t s_off = 0, rm_off = 0, out_off = 0, dir_off = 0, row_off = 0, mv = 0, it = 0, nb = 0;
+  std::vector<uint32_t> pkey((size_t)np);
+  std::vector<int32_t> first_item((size_t)np + 1);
   for (int64_t p = p0; p < p1; p++) {
     const int64_t n = sdo[p + 1] - sdo[p], m = tdo[p + 1] - tdo[p];
     PairDesc &d = descs[p - p0];
@@ -211,37 +249,46 @@ void Chunk::fill_host(const int64_t *sdo, const int64_t *tdo, char *host) const 
       d.row_off = -1;
     }
     if (nw_is_big(n)) big[nb++] = (int32_t)(p - p0);
-    if (n > 0 && m > 0)
-      for (int64_t i0 = 0; i0 < n; i0 += item_rows) {
-        SimItem &x = items[it++];
-        x.pair = (int32_t)(p - p0);
-        x.i0 = (int32_t)i0;
-        x.i1 = (int32_t)std::min<int64_t>(n, i0 + item_rows);
-        x.n = d.n;
-        x.m = d.m;
-        x.pad = 0;
-        x.src_sent0 = d.src_sent0;
-        x.tgt_sent0 = d.tgt_sent0;
-        x.s_off = d.s_off;
-        x.rm_off = d.rm_off;
-      }
+    first_item[p - p0] = (int32_t)it;
+    if (n > 0 && m > 0) it += (n + item_rows - 1) / item_rows;
+    pkey[p - p0] = clamp_key(n * m);
     moff[p - p0] = mv;
     mv += n + m;
     s_off += score_block(n, m);
     rm_off += n * m;
     out_off += std::min(n, m);
   }
+  first_item[np] = (int32_t)it;
   // the largest pairs first in the NW launch, and the largest similarity
   // items (rows x target sentences) first, so each kernel's last workgroups
   // are short ones
-  for (int64_t q = 0; q < np; q++) order[q] = (int32_t)q;
-  std::stable_sort(order, order + np, [&](int32_t x, int32_t y) {
-    return (int64_t)descs[x].n * descs[x].m > (int64_t)descs[y].n * descs[y].m;
-  });
-  std::stable_sort(items, items + it, [&](const SimItem &x, const SimItem &y) {
-    const int64_t wx = (int64_t)(x.i1 - x.i0) * descs[x.pair].m, wy = (int64_t)(y.i1 - y.i0) * descs[y.pair].m;
-    return wx > wy;
-  });
+  order_desc(pkey.data(), np, order);
+  std::vector<uint32_t> ikey((size_t)it);
+  std::vector<int32_t> ipair((size_t)it), iorder((size_t)it);
+  for (int64_t q = 0; q < np; q++) {
+    const int32_t n = descs[q].n, m = descs[q].m;
+    for (int32_t k = first_item[q], i0 = 0; k < first_item[q + 1]; k++, i0 += item_rows) {
+      ikey[k] = clamp_key((int64_t)(std::min(n, i0 + item_rows) - i0) * m);
+      ipair[k] = (int32_t)q;
+    }
+  }
+  order_desc(ikey.data(), it, iorder.data());
+  for (int64_t k = 0; k < it; k++) {
+    const int32_t src = iorder[k], q = ipair[src];
+    const PairDesc &d = descs[q];
+    const int32_t i0 = (src - first_item[q]) * item_rows;
+    SimItem &x = items[k];
+    x.pair = q;
+    x.i0 = i0;
+    x.i1 = std::min(d.n, i0 + item_rows);
+    x.n = d.n;
+    x.m = d.m;
+    x.pad = 0;
+    x.src_sent0 = d.src_sent0;
+    x.tgt_sent0 = d.tgt_sent0;
+    x.s_off = d.s_off;
+    x.rm_off = d.rm_off;
+  }
 }
 
 }  // namespace ym
