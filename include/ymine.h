@@ -218,6 +218,27 @@ ym_status ym_mine_device(ym_ctx *ctx, const ym_lexicon *lex, const ym_device_bat
                          const ym_params *params, void *workspace, size_t workspace_bytes,
                          const ym_device_out *out, void *stream);
 
+/* Allocation-free form of ym_mine_device, for callers that cannot allocate
+ * device or pinned host memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same batch, parameters, outputs,
+ * stream semantics and results as ym_mine_device; the workspace is instead a
+ * static device array of YM_STATIC_SCRATCH_BYTES per device, which the library
+ * holds from the first ym_create on that device until the process ends.  The
+ * call makes no hipMalloc, hipHostMalloc or hipFree: the score table and the
+ * pinned plan staging buffer are set up by ym_create, and the batch is split
+ * into chunks whose plans fit that staging buffer.
+ * Errors: as ym_mine_device, and YM_ENOMEM (before any work is enqueued) when
+ * ym_mine_device_workspace_min() of the batch exceeds YM_STATIC_SCRATCH_BYTES,
+ * that is when 16 bytes per source token plus the largest pair's workspace do
+ * not fit.  Every call on one device shares that device's array, and a call
+ * leaves its contents in place (nothing in it needs to start cleared): calls
+ * whose work overlaps on one device -- from several threads or contexts, or on
+ * streams that are not ordered one after the other -- race and give undefined
+ * results.  Order them (one stream, or events) to use this form. */
+#define YM_STATIC_SCRATCH_BYTES ((size_t)256 << 20)
+ym_status ym_mine_device_static(ym_ctx *ctx, const ym_lexicon *lex, const ym_device_batch *batch,
+                                const ym_params *params, const ym_device_out *out, void *stream);
+
 /* --------------------------------------------------- parity / debug entries */
 
 /* Similarity kernel alone on a host batch: S, m_s, m_t of every pair, row-

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libymine.so")
-SOURCES = ["kernels.hip", "runtime.hip", "api.hip", "server.hip"]
+SOURCES = ["kernels.hip", "runtime.hip", "api.hip", "server.hip", "static_ws.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

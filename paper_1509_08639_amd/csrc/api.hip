@@ -317,6 +317,19 @@ size_t ym_mine_device_workspace_min(const int64_t *sdo, const int64_t *tdo, int6
 
 ym_status ym_mine_device(ym_ctx *c, const ym_lexicon *L, const ym_device_batch *b, const ym_params *prm, void *workspace,
                          size_t workspace_bytes, const ym_device_out *out, void *stream) {
+  if (!c) return fail(YM_EINVAL, "NULL argument");
+  hipSetDevice(c->device);
+  std::lock_guard<std::mutex> lk(c->mu);
+  return mine_device(c, L, b, prm, workspace, workspace_bytes, out, stream, 0);
+}
+}  // extern "C"
+
+namespace ym {
+// ym_mine_device with the context lock held.  `plan_cap` (0: none) bounds the
+// plan bytes of each chunk, so its upload fits the context's pinned staging
+// buffer without growing it.
+ym_status mine_device(ym_ctx *c, const ym_lexicon *L, const ym_device_batch *b, const ym_params *prm, void *workspace,
+                      size_t workspace_bytes, const ym_device_out *out, void *stream, size_t plan_cap) {
   if (!c || !L || !b || !out) return fail(YM_EINVAL, "NULL argument");
   ym_status s;
   if ((s = check_params(prm))) return s;
@@ -327,12 +340,10 @@ ym_status ym_mine_device(ym_ctx *c, const ym_lexicon *L, const ym_device_batch *
   if (b->n_src_tok < 0 || b->n_tgt_tok < 0) return fail(YM_EINVAL, "negative token count");
   if (!workspace && b->n_pairs) return fail(YM_EINVAL, "NULL workspace");
   hipStream_t st = (hipStream_t)stream;
-  hipSetDevice(c->device);
-  std::lock_guard<std::mutex> lk(c->mu);
   const size_t head = trans_bytes(b->n_src_tok);
   if (workspace_bytes < head + 256) return fail(YM_ENOMEM, "workspace smaller than the token translations (%zu bytes)", head);
   std::vector<std::pair<int64_t, int64_t>> chunks;
-  if ((s = plan_chunks(b->src_doc_off, b->tgt_doc_off, b->n_pairs, workspace_bytes - head, chunks))) return s;
+  if ((s = plan_chunks(b->src_doc_off, b->tgt_doc_off, b->n_pairs, workspace_bytes - head, chunks, plan_cap))) return s;
   if ((s = ensure_table(c, prm, st))) return s;
   DevBatch d;
   d.src_sent_off = b->src_sent_off;
@@ -347,15 +358,16 @@ ym_status ym_mine_device(ym_ctx *c, const ym_lexicon *L, const ym_device_batch *
     const hipError_t e = launch_fill_i32(out->status, 0, 1, st);
     if (e) return hip_fail(e, "status clear");
   }
-  if (b->n_pairs == 0) {
-    hipError_t e = hipMemsetAsync(out->pair_off, 0, 8, st);
-    return e ? hip_fail(e, "memset") : YM_OK;
+  if (b->n_pairs == 0) {  // pair_off[0] = 0 (two int32 zeros, by a fill kernel)
+    hipError_t e = launch_fill_i32((int32_t *)out->pair_off, 0, 2, st);
+    return e ? hip_fail(e, "pair_off clear") : YM_OK;
   }
   // the first chunk's plan goes up on the upload stream while the tokens are translated
   char *ws = (char *)workspace + head;
   Chunk first;
   first.layout(b->src_doc_off, b->tgt_doc_off, chunks[0].first, chunks[0].second, c->item_rows);
   if (first.bytes > workspace_bytes - head) return fail(YM_ENOMEM, "workspace too small");
+  if (plan_cap && first.host_bytes > plan_cap) return fail(YM_ENOMEM, "chunk plan larger than the staging buffer");
   if ((s = upload_plan(c, b->src_doc_off, b->tgt_doc_off, first, ws, st, nullptr, true))) return s;
   if ((s = translate_batch(c, L, d, (char *)workspace, st))) return s;
   hipError_t e = hipStreamWaitEvent(st, c->ev_up, 0);
@@ -365,11 +377,15 @@ ym_status ym_mine_device(ym_ctx *c, const ym_lexicon *L, const ym_device_batch *
     if (k) ch.layout(b->src_doc_off, b->tgt_doc_off, chunks[k].first, chunks[k].second, c->item_rows);
     const Chunk &cc = k ? ch : first;
     if (cc.bytes > workspace_bytes - head) return fail(YM_ENOMEM, "workspace too small");
+    if (plan_cap && cc.host_bytes > plan_cap) return fail(YM_ENOMEM, "chunk plan larger than the staging buffer");
     if ((s = run_chunk(c, L, d, prm, b->src_doc_off, b->tgt_doc_off, cc, ws, *out, st, nullptr, nullptr, k == 0)))
       return s;
   }
   return YM_OK;
 }
+}  // namespace ym
+
+extern "C" {
 
 // A device buffer owned by one call (freed on every return path).
 struct CallBuf : DevBuf {

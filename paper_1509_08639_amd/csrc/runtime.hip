@@ -343,6 +343,16 @@ ym_status ym_create(int device, size_t hbm_budget_bytes, ym_ctx **out) {
     delete c;
     return hip_fail(e, "hipEventCreate / hipStreamCreate");
   }
+  // the score table, the plan staging buffer and this device's static scratch
+  // are set up here, so the allocation-free entry point finds them in place
+  ym_status s0 = c->table.reserve((size_t)kTabLen * kTabLen * kTabLen * kTabLen * 4, true);
+  if (!s0) s0 = c->stage.buf.reserve(kStagingBytes);
+  if (!s0) s0 = static_scratch_init(device);
+  if (s0) {
+    const std::string msg = ym_last_error();
+    ym_destroy(c);
+    return fail(s0, "%s", msg.c_str());
+  }
   size_t free_b = 0, total_b = 0;
   if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = total_b = 0;
   c->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.8 * (double)free_b);
@@ -612,9 +622,19 @@ ym_status check_pair_shape(int64_t n, int64_t m, int64_t pair) {
   return YM_OK;
 }
 
-// Split pairs [0, n_pairs) into chunks whose workspace fits `ws_bytes`.
+// Plan bytes of one pair (the part of pair_bytes that is uploaded from the
+// host: descriptor, similarity items, move offset, large-pair entry, NW order).
+static size_t pair_plan_bytes(int64_t n, int64_t m) {
+  (void)m;
+  return sizeof(PairDesc) + (size_t)((n + kMinItemRows - 1) / kMinItemRows) * sizeof(SimItem) + 8 + 4 +
+         (nw_is_big(n) ? 4 : 0);
+}
+static const size_t kPlanSlack = 6 * 256;  // alignment padding of the plan's five regions, and their minimum sizes
+
+// Split pairs [0, n_pairs) into chunks whose workspace fits `ws_bytes` and,
+// when `plan_cap` is not 0, whose plan fits `plan_cap` bytes.
 ym_status plan_chunks(const int64_t *sdo, const int64_t *tdo, int64_t n_pairs, size_t ws_bytes,
-                      std::vector<std::pair<int64_t, int64_t>> &chunks) {
+                      std::vector<std::pair<int64_t, int64_t>> &chunks, size_t plan_cap) {
   chunks.clear();
   int64_t p = 0;
   for (int64_t q = 0; q < n_pairs; q++) {
@@ -622,15 +642,19 @@ ym_status plan_chunks(const int64_t *sdo, const int64_t *tdo, int64_t n_pairs, s
     if (st) return st;
   }
   while (p < n_pairs) {
-    size_t acc = kChunkSlack;
+    size_t acc = kChunkSlack, plan = kPlanSlack;
     int64_t q = p;
     while (q < n_pairs) {
-      const size_t b = pair_bytes(sdo[q + 1] - sdo[q], tdo[q + 1] - tdo[q]);
-      if (q > p && acc + b > ws_bytes) break;
+      const int64_t n = sdo[q + 1] - sdo[q], m = tdo[q + 1] - tdo[q];
+      const size_t b = pair_bytes(n, m), h = plan_cap ? pair_plan_bytes(n, m) : 0;
+      if (q > p && (acc + b > ws_bytes || (plan_cap && plan + h > plan_cap))) break;
       acc += b;
+      plan += h;
       q++;
     }
     if (acc > ws_bytes) return fail(YM_ENOMEM, "pair %lld needs %zu workspace bytes, %zu given", (long long)p, acc, ws_bytes);
+    if (plan_cap && plan > plan_cap)
+      return fail(YM_ENOMEM, "pair %lld needs %zu plan bytes, %zu available", (long long)p, plan, plan_cap);
     chunks.push_back({p, q});
     p = q;
   }

@@ -73,7 +73,7 @@ ym_status ensure_table(ym_ctx *c, const ym_params *p, hipStream_t st);
 // Resolve the batch's source tokens into `head` (trans_bytes(n_src_tok) bytes) and point b.trans at it.
 ym_status translate_batch(ym_ctx *c, const ym_lexicon *L, DevBatch &b, char *head, hipStream_t st);
 ym_status plan_chunks(const int64_t *sdo, const int64_t *tdo, int64_t n_pairs, size_t ws_bytes,
-                      std::vector<std::pair<int64_t, int64_t>> &chunks);
+                      std::vector<std::pair<int64_t, int64_t>> &chunks, size_t plan_cap = 0);
 // Pinned staging buffer for plan uploads and the event that marks its last
 // upload as done (the buffer is rewritten only after that event).
 struct Staging {
@@ -87,6 +87,17 @@ struct Staging {
 // `st`, recording c->ev_up when done (the caller makes `st` wait for it).
 ym_status upload_plan(ym_ctx *c, const int64_t *sdo, const int64_t *tdo, const Chunk &ch, char *ws, hipStream_t st,
                       Staging *stg, bool side);
+// ym_mine_device with the context lock held; `plan_cap` (0: none) bounds each
+// chunk's plan so that its upload fits the pinned staging buffer as it is.
+ym_status mine_device(ym_ctx *c, const ym_lexicon *L, const ym_device_batch *b, const ym_params *prm, void *workspace,
+                      size_t workspace_bytes, const ym_device_out *out, void *stream, size_t plan_cap);
+// Pinned staging reserved by ym_create for plan uploads (never grown by the
+// allocation-free entry point).
+constexpr size_t kStagingBytes = (size_t)8 << 20;
+// The allocation-free entry point's device scratch: look up (once per device,
+// with that device current) where this device's copy of the static array lives.
+ym_status static_scratch_init(int device);
+
 // Enqueue one chunk: its plan upload (unless `plan_ready`), then the kernels.
 ym_status run_chunk(ym_ctx *c, const ym_lexicon *L, const DevBatch &b, const ym_params *prm, const int64_t *sdo,
                     const int64_t *tdo, const Chunk &ch, char *ws, const ym_device_out &out, hipStream_t st,

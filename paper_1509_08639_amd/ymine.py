@@ -24,6 +24,8 @@ YM_EBUDGET = -4
 YM_ECANCELLED = -5
 YM_ENOTFOUND = -6
 
+STATIC_SCRATCH_BYTES = 256 << 20  # YM_STATIC_SCRATCH_BYTES: workspace of ym_mine_device_static
+
 # Every symbol declared in include/ymine.h.
 EXPORTS = [
     "ym_create", "ym_destroy", "ym_last_error", "ym_version", "ym_lexicon_load", "ym_lexicon_free",
@@ -32,7 +34,7 @@ EXPORTS = [
     "ym_nw_align", "ym_tune", "ym_mine_bidirectional", "ym_set_tuning", "ym_get_tuning", "ym_autotune",
     "ym_profile_enable", "ym_profile_read", "ym_server_start", "ym_submit", "ym_poll", "ym_server_next_done", "ym_cancel",
     "ym_server_stop",
-    "ym_server_stats", "ym_server_graph_stats", "ym_check_pair", "ym_set_wait_limit",
+    "ym_server_stats", "ym_server_graph_stats", "ym_check_pair", "ym_set_wait_limit", "ym_mine_device_static",
 ]
 
 
@@ -113,6 +115,7 @@ def lib():
     L.ym_mine_device_workspace_min.argtypes = [P(i64), P(i64), i64, i64]
     L.ym_mine_device_workspace_min.restype = C.c_size_t
     L.ym_mine_device.argtypes = [vp, vp, P(DeviceBatch), P(Params), vp, C.c_size_t, P(DeviceOut), vp]
+    L.ym_mine_device_static.argtypes = [vp, vp, P(DeviceBatch), P(Params), P(DeviceOut), vp]
     L.ym_similarity.argtypes = [vp, vp, P(Batch), P(Params), P(f32), P(i32), P(i32)]
     L.ym_nw_align.argtypes = [vp, P(f32), P(i32), P(i32), i64, f32, f32, P(f32), C.c_char_p, P(i32),
                               P(P(Result))]
@@ -416,6 +419,14 @@ class DeviceMiner:
         st = stream if stream is not None else self.torch.cuda.current_stream().cuda_stream
         _check(lib().ym_mine_device(self.ctx.h, self.lex.h, C.byref(self.b), C.byref(p), self.ws.data_ptr(),
                                     self.ws_bytes, C.byref(self.o), vp(st)))
+
+    def run_static(self, w, gap, threshold, stream=None):
+        """Enqueue one mining pass through the allocation-free entry point
+        (ym_mine_device_static: the library's static scratch as workspace)."""
+        p = params(w, gap, threshold)
+        st = stream if stream is not None else self.torch.cuda.current_stream().cuda_stream
+        _check(lib().ym_mine_device_static(self.ctx.h, self.lex.h, C.byref(self.b), C.byref(p), C.byref(self.o),
+                                           vp(st)))
 
     def result(self) -> dict:
         """The last pass's result; raises YmError(YM_EDEVICE) if a pair could not be completed."""
