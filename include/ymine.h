@@ -270,6 +270,24 @@ ym_status ym_tune(ym_ctx *ctx, const ym_lexicon *lex, const ym_batch *batch, con
                   int32_t n_gaps, const float *taus, int32_t n_taus, const int64_t *truth_off,
                   const int32_t *truth_src, const int32_t *truth_tgt, int64_t *n_mined, int64_t *n_correct);
 
+/* The parameter choice of the tuned miner: the (gap, threshold) entry of a
+ * sweep with the highest F1 against the reference pairs (the paper tunes
+ * penalty and threshold but gives no objective; F1 is this library's reading).
+ * n_mined / n_correct are ym_tune's arrays (n_gaps x n_taus, row-major),
+ * n_truth the number of reference pairs (truth_off[n_pairs]).  F1 =
+ * 2 correct / (mined + n_truth) (0 when both are 0), compared exactly in
+ * integers; among equal values the first entry in row-major order (the
+ * earliest gap, then the earliest threshold) is chosen.  Host only, no device
+ * work.  YM_EINVAL for NULL pointers, empty sweeps or counts that are not
+ * 0 <= correct <= min(mined, n_truth). */
+typedef struct {
+  int32_t gap_index, tau_index;
+  int64_t n_mined, n_correct;
+  double precision, recall, f1;
+} ym_tune_choice;
+ym_status ym_tune_select(const int64_t *n_mined, const int64_t *n_correct, int32_t n_gaps, int32_t n_taus,
+                         int64_t n_truth, ym_tune_choice *out);
+
 /* Bidirectional mining (Section 5: a second classifier trained in the other
  * direction, results joined without duplicates).  Mines the batch forward
  * with (lex_fwd, fwd) and with source and target swapped with (lex_rev, rev),
@@ -288,7 +306,9 @@ ym_status ym_mine_bidirectional(ym_ctx *ctx, const ym_lexicon *lex_fwd, const ym
 typedef struct {
   int32_t sim_kernel;         /* similarity kernel: 1 one lane per target sentence (default); 2 the same,
                                  with the reads of target sentences longer than 32 tokens split over the
-                                 lanes a chunk leaves spare; 0 bit-sliced tiles */
+                                 lanes a chunk leaves spare; 0 bit-sliced tiles of one wave; 3 and 4
+                                 bit-sliced 64-row tiles shared by four waves, target chunks of at most
+                                 1,280 (3) or 2,048 (4) tokens */
   int32_t item_rows;          /* source sentences per similarity work item: 64, 128 (default) or 256 */
   int32_t nw_pairs_per_group; /* document pairs per NW workgroup, one wave each: 1 (default), 2 or 4 */
 } ym_tuning;

@@ -485,6 +485,34 @@ ym_status ym_tune(ym_ctx *c, const ym_lexicon *L, const ym_batch *b, const float
   return YM_OK;
 }
 
+ym_status ym_tune_select(const int64_t *n_mined, const int64_t *n_correct, int32_t n_gaps, int32_t n_taus,
+                         int64_t n_truth, ym_tune_choice *out) {
+  if (!n_mined || !n_correct || !out) return fail(YM_EINVAL, "NULL argument");
+  if (n_gaps < 1 || n_taus < 1) return fail(YM_EINVAL, "need at least one gap and one threshold");
+  if (n_truth < 0) return fail(YM_EINVAL, "n_truth < 0");
+  const int64_t K = (int64_t)n_gaps * n_taus;
+  for (int64_t k = 0; k < K; k++)
+    if (n_correct[k] < 0 || n_correct[k] > n_mined[k] || n_correct[k] > n_truth)
+      return fail(YM_EINVAL, "entry %lld: counts must satisfy 0 <= correct <= min(mined, n_truth)", (long long)k);
+  // F1 = 2 c / (m + T), compared exactly: c_a (m_b + T) > c_b (m_a + T); the
+  // first entry in row-major order wins among equal values
+  int64_t best = 0;
+  for (int64_t k = 1; k < K; k++) {
+    const __int128 db = (__int128)n_mined[best] + n_truth, dk = (__int128)n_mined[k] + n_truth;
+    const __int128 lhs = (__int128)n_correct[k] * (db > 0 ? db : 1), rhs = (__int128)n_correct[best] * (dk > 0 ? dk : 1);
+    if (lhs > rhs) best = k;
+  }
+  const int64_t mb = n_mined[best], cb = n_correct[best];
+  out->gap_index = (int32_t)(best / n_taus);
+  out->tau_index = (int32_t)(best % n_taus);
+  out->n_mined = mb;
+  out->n_correct = cb;
+  out->precision = mb > 0 ? (double)cb / (double)mb : 0.0;
+  out->recall = n_truth > 0 ? (double)cb / (double)n_truth : 0.0;
+  out->f1 = mb + n_truth > 0 ? 2.0 * (double)cb / (double)(mb + n_truth) : 0.0;
+  return YM_OK;
+}
+
 ym_status ym_mine_bidirectional(ym_ctx *c, const ym_lexicon *Lf, const ym_lexicon *Lr, const ym_batch *b,
                                 const ym_params *pf, const ym_params *pr, ym_result **out) {
   if (!out) return fail(YM_EINVAL, "NULL out");
@@ -564,7 +592,7 @@ ym_status ym_mine_bidirectional(ym_ctx *c, const ym_lexicon *Lf, const ym_lexico
 // ------------------------------------------------------------ tuning of launches
 static ym_status check_tuning(const ym_tuning *t) {
   if (!t) return fail(YM_EINVAL, "NULL tuning");
-  if (t->sim_kernel < 0 || t->sim_kernel > 2) return fail(YM_EINVAL, "sim_kernel must be 0, 1 or 2");
+  if (t->sim_kernel < 0 || t->sim_kernel > 4) return fail(YM_EINVAL, "sim_kernel must be 0, 1, 2, 3 or 4");
   if (t->item_rows != 64 && t->item_rows != 128 && t->item_rows != 256)
     return fail(YM_EINVAL, "item_rows must be 64, 128 or 256");
   if (t->nw_pairs_per_group != 1 && t->nw_pairs_per_group != 2 && t->nw_pairs_per_group != 4)
@@ -655,7 +683,8 @@ ym_status ym_autotune(ym_ctx *c, const ym_lexicon *L, const ym_batch *b, const y
   ym_tuning win = before;
   double win_ms = 1e300;
   // similarity kernel and item size first (the NW launch is the same for all of them) ...
-  for (int v = 2; v >= 0 && !s; v--)
+  for (int v : {4, 3, 2, 1, 0}) {
+    if (s) break;
     for (int rows : {64, 128, 256}) {
       const ym_tuning t{v, rows, before.nw_pairs_per_group};
       double ms = 0;
@@ -665,6 +694,7 @@ ym_status ym_autotune(ym_ctx *c, const ym_lexicon *L, const ym_batch *b, const y
         win = t;
       }
     }
+  }
   // ... then the NW workgroup size with that choice
   for (int ppg : {1, 2, 4}) {
     if (s) break;

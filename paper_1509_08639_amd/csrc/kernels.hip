@@ -1487,6 +1487,507 @@ __global__ __launch_bounds__(kTileThreads) void sim_tile_kernel(SimArgs a) {
   }
 }
 
+// ------------------------------------------- (a) similarity, kernels 3 and 4
+// Bit-sliced tiles worked by four waves together.  A tile is one 64-row
+// strip of a pair (rows r0 .. r0 + R - 1) against one chunk of its target
+// sentences (at most 64 sentences and TC tokens; kernel 3 takes TC = 1280,
+// three workgroups per CU, kernel 4 TC = 2048, two per CU, which fills the
+// chunk's 64 lanes with sentences of the scale workload's lengths).  The
+// chunk's distinct target ids get dense local ids through an LDS hash, and
+//   D[id] = set of the chunk's sentences holding id (bit j: sentence j0 + j);
+// the source pass builds
+//   B[id] = set of the strip's rows whose translation set X_i holds id.
+// Counts are kept in bit-sliced counters (plane p holds bit p of 64 counts):
+//   source pass, lane = row i: for every position q, the OR of D over the
+//     translations of s_i[q] is the set of sentences j that meet T(s_i[q]);
+//     adding it counts m_s(i, .) for the 64 sentences at once;
+//   target pass, lane = sentence j: for every position p, B[id(t_j[p])] is the
+//     set of rows whose X_i holds t_j[p]; adding it counts m_t(., j) for the
+//     64 rows at once.
+// Sets are added four at a time with carry-save adders.  The waves split both
+// passes by position (wave w takes source positions q = w mod 4 and target
+// positions in blocks 4w .. 4w + 3 mod 16); their partial counters are summed
+// through LDS, the m_s planes transposed (lane = sentence), and each wave
+// scores a quarter of the tile's rows from the score table.  Tiles whose
+// sentences exceed 63 tokens (counts need 11 planes) run both passes on one
+// wave and score cell by cell.
+constexpr int kBitsWaves = 4;
+constexpr int kBitsThreads = 64 * kBitsWaves;
+constexpr int kBitsNarrow = 6;  // planes for counts <= 63
+constexpr int kBitsWide = 11;   // planes for counts <= 2047 (sentences of at most 1024 tokens)
+
+template <int TC>
+struct BitsLds {
+  // region H: the chunk's id hash {key, local id}; once the source pass is
+  // done, the partial counters of the waves
+  union {
+    int2 ent[2 * TC];
+    uint64_t xch[2 * (kBitsWaves - 1) * kBitsNarrow * 64];
+  } h;
+  // region DB: D and B (id 0: none, always 0; id TC + 1: where lookups that
+  // found nothing mark); once the target pass is done, the summed m_s
+  // (row-major), the transposed m_s and m_t (lane = sentence)
+  union {
+    struct {
+      uint64_t D[TC + 2];
+      uint64_t B[TC + 2];
+    } db;
+    uint64_t fin[3 * kBitsWide * 64];
+  } d;
+  __align__(16) uint16_t tdoc[TC + 3 * kJcap];  // local ids, each sentence padded to a multiple of 4 (id 0)
+  uint8_t tsen[TC + 3 * kJcap];                  // sentence of each staged position
+  uint16_t toff[kJcap], toff_o[kJcap + 1], tlen[kJcap];
+  int ends[kJcap];
+  int j1, nlid, npad, bmax;
+};
+
+__device__ __forceinline__ uint32_t bits_slot(int32_t x, uint32_t ns) { return __umulhi(hash32(x), ns); }
+
+// Insert target id x (>= 0) into a hash of ns slots: its slot, and whether x was new.
+__device__ __forceinline__ int bits_insert(int2 *ent, uint32_t ns, int32_t x, bool &fresh) {
+  uint32_t h = bits_slot(x, ns);
+  for (;;) {  // at most TC distinct keys in 2 TC slots
+    const int prev = atomicCAS(&ent[h].x, kEmpty, x);
+    if (prev == kEmpty || prev == x) {
+      fresh = prev == kEmpty;
+      return (int)h;
+    }
+    h = h + 1 == ns ? 0 : h + 1;
+  }
+}
+
+// Local ids of K target ids at once (0: not an id of the chunk, or x < 0):
+// every first probe is issued before any second one.
+template <int K>
+__device__ __forceinline__ void bits_find(const int2 *ent, uint32_t ns, const int32_t (&x)[K], int (&lid)[K]) {
+  uint32_t h[K];
+  int2 e[K];
+  bool p[K];
+#pragma unroll
+  for (int k = 0; k < K; k++) {
+    h[k] = bits_slot(x[k], ns);
+    e[k] = ent[h[k]];
+  }
+  bool any = false;
+#pragma unroll
+  for (int k = 0; k < K; k++) {
+    p[k] = x[k] >= 0 && e[k].x != x[k] && e[k].x != kEmpty;
+    any |= p[k];
+  }
+  while (any) {
+    any = false;
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+      if (p[k]) {
+        h[k] = h[k] + 1 == ns ? 0 : h[k] + 1;
+        e[k] = ent[h[k]];
+        p[k] = e[k].x != x[k] && e[k].x != kEmpty;
+        any |= p[k];
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < K; k++) lid[k] = (x[k] >= 0 && e[k].x == x[k]) ? e[k].y : 0;
+}
+
+// Carry-save adder: a + b + c = s + 2 carry, bit by bit.
+__device__ __forceinline__ void bits_csa(uint32_t &s, uint32_t &carry, uint32_t a, uint32_t b, uint32_t c) {
+  const uint32_t t = a ^ b;
+  s = t ^ c;
+  carry = (t & c) | (~t & a);
+}
+
+// Add four sets (one bit per counter) into NPL bit-sliced planes.  The caller
+// guarantees that no count exceeds 2^NPL - 1.
+template <int NPL>
+__device__ __forceinline__ void bits_add4(uint32_t (&P)[NPL], uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3) {
+  uint32_t s, ca, cb, c4;
+  bits_csa(s, ca, P[0], x0, x1);     // P0 + x0 + x1 = s + 2 ca
+  bits_csa(P[0], cb, s, x2, x3);     // s + x2 + x3 = P0' + 2 cb
+  bits_csa(P[1], c4, P[1], ca, cb);  // P1 + ca + cb = P1' + 2 c4
+#pragma unroll
+  for (int k = 2; k < NPL; k++) {
+    const uint32_t t = P[k] & c4;
+    P[k] ^= c4;
+    c4 = t;
+  }
+}
+
+// P += Q, counter by counter (ripple carry over the planes).
+template <int NPL>
+__device__ __forceinline__ void bits_add_counters(uint32_t (&P)[NPL], const uint32_t (&Q)[NPL]) {
+  uint32_t c = 0;
+#pragma unroll
+  for (int k = 0; k < NPL; k++) {
+    uint32_t s, cn;
+    bits_csa(s, cn, P[k], Q[k], c);
+    P[k] = s;
+    c = cn;
+  }
+}
+
+// End of the target chunk starting at sentence j0: the largest j1 <= j0 + 64
+// whose sentences [j0, j1) hold at most TC tokens (at least one sentence);
+// lane L of the calling wave also keeps the end of the chunk's sentence L
+// relative to the chunk's first token (clamped to [0, 2^30]).
+template <int TC>
+__device__ __forceinline__ void bits_chunk_end(const int64_t *toffs, int j0, int m, int64_t n_tok, int *out, int *ends) {
+  const int lane = threadIdx.x & 63;
+  const int64_t base = clamp64(toffs[j0], 0, n_tok);
+  const int jj = j0 + 1 + lane;
+  const bool ok = jj <= min(m, j0 + kJcap);
+  const int64_t e = ok ? clamp64(toffs[jj], 0, n_tok) - base : 0;
+  const uint64_t bal = __ballot(ok && e <= TC);
+  const int lead = ~bal == 0 ? 64 : __builtin_ctzll(~bal);
+  if (lane == 0) *out = j0 + max(1, lead);
+  ends[lane] = (int)clamp64(e, 0, 1 << 30);
+}
+
+// Source pass over the positions q = q0 + qs (4 u + k) of this lane's row
+// (record base sb, length al; amax: the longest row of the strip): marks B and
+// adds, per position, the set of the chunk's sentences meeting its
+// translations into the planes (lo: sentences 0-31, hi: 32-63).
+template <int NPL, int TC>
+__device__ __forceinline__ void bits_s_pass(const SimArgs &a, BitsLds<TC> &L, int64_t sb, int al, int amax, int q0,
+                                            int qs, uint32_t (&lo)[NPL], uint32_t (&hi)[NPL]) {
+  constexpr uint32_t NS = 2 * TC;
+  const int lane = threadIdx.x & 63;
+  const unsigned long long rowbit = 1ull << lane;
+  unsigned long long *B = reinterpret_cast<unsigned long long *>(L.d.db.B);
+  const uint64_t *D = L.d.db.D;
+  auto fetch = [&](int u, int4 (&r)[4]) {
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      const int q = q0 + qs * (4 * u + k);
+      r[k] = q < al ? a.trans[sb + q] : make_int4(-1, -1, -1, -1);
+    }
+  };
+  int4 ra[4];
+  fetch(0, ra);
+  for (int u = 0; q0 + qs * 4 * u < amax; u++) {
+    int4 rb[4];
+    fetch(u + 1, rb);
+    int32_t x[16];
+    bool far = false;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      const bool f = ra[k].x == -2;  // more than four translations: looked up below
+      far |= f;
+      x[4 * k] = f ? -1 : ra[k].x;
+      x[4 * k + 1] = f ? -1 : ra[k].y;
+      x[4 * k + 2] = f ? -1 : ra[k].z;
+      x[4 * k + 3] = f ? -1 : ra[k].w;
+    }
+    int lid[16];
+    bits_find<16>(L.h.ent, NS, x, lid);
+#pragma unroll
+    for (int k = 0; k < 16; k++) atomicOr(&B[lid[k] ? lid[k] : TC + 1], rowbit);
+    uint64_t c[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) c[k] = (D[lid[4 * k]] | D[lid[4 * k + 1]]) | (D[lid[4 * k + 2]] | D[lid[4 * k + 3]]);
+    if (far) {
+#pragma unroll
+      for (int k = 0; k < 4; k++) {
+        if (ra[k].x == -2) {
+          for (int e = 0; e < ra[k].z; e++) {
+            const int32_t y[1] = {a.lex.vals[ra[k].y + e]};
+            int l[1];
+            bits_find<1>(L.h.ent, NS, y, l);
+            atomicOr(&B[l[0] ? l[0] : TC + 1], rowbit);
+            c[k] |= D[l[0]];
+          }
+        }
+      }
+    }
+    bits_add4<NPL>(lo, (uint32_t)c[0], (uint32_t)c[1], (uint32_t)c[2], (uint32_t)c[3]);
+    bits_add4<NPL>(hi, (uint32_t)(c[0] >> 32), (uint32_t)(c[1] >> 32), (uint32_t)(c[2] >> 32), (uint32_t)(c[3] >> 32));
+#pragma unroll
+    for (int k = 0; k < 4; k++) ra[k] = rb[k];
+  }
+}
+
+// Target pass over blocks of four positions k0, k0 + ks, ... of this lane's
+// sentence j: adds B of each position's id into the planes (lo: rows 0-31,
+// hi: 32-63).
+template <int NPL, int TC>
+__device__ __forceinline__ void bits_t_pass(const BitsLds<TC> &L, int nj, int k0, int ks, uint32_t (&lo)[NPL],
+                                            uint32_t (&hi)[NPL]) {
+  const int j = threadIdx.x & 63;
+  const bool jok = j < nj;
+  const int bl = jok ? L.tlen[j] : 0;
+  const uint16_t *tp = L.tdoc + (jok ? L.toff[j] : 0);
+  const uint64_t *B = L.d.db.B;
+  const int bmax = L.bmax;
+  for (int k = k0; k < bmax; k += 2 * ks) {
+    uint64_t x[8];
+#pragma unroll
+    for (int g = 0; g < 2; g++) {
+      const int kk = k + g * ks;
+      uint2 ids = make_uint2(0u, 0u);  // id 0: B[0] = 0
+      if (kk < bl) ids = *reinterpret_cast<const uint2 *>(tp + kk);
+      x[4 * g] = B[ids.x & 0xFFFFu];
+      x[4 * g + 1] = B[ids.x >> 16];
+      x[4 * g + 2] = B[ids.y & 0xFFFFu];
+      x[4 * g + 3] = B[ids.y >> 16];
+    }
+#pragma unroll
+    for (int g = 0; g < 2; g++) {
+      bits_add4<NPL>(lo, (uint32_t)x[4 * g], (uint32_t)x[4 * g + 1], (uint32_t)x[4 * g + 2], (uint32_t)x[4 * g + 3]);
+      bits_add4<NPL>(hi, (uint32_t)(x[4 * g] >> 32), (uint32_t)(x[4 * g + 1] >> 32), (uint32_t)(x[4 * g + 2] >> 32),
+                     (uint32_t)(x[4 * g + 3] >> 32));
+    }
+  }
+}
+
+template <int NPL>
+__device__ __forceinline__ void bits_store(uint64_t *dst, const uint32_t (&lo)[NPL], const uint32_t (&hi)[NPL]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int p = 0; p < NPL; p++) dst[p * 64 + lane] = ((uint64_t)hi[p] << 32) | lo[p];
+}
+
+template <int NPL>
+__device__ __forceinline__ void bits_load(const uint64_t *src, uint32_t (&lo)[NPL], uint32_t (&hi)[NPL]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int p = 0; p < NPL; p++) {
+    const uint64_t v = src[p * 64 + lane];
+    lo[p] = (uint32_t)v;
+    hi[p] = (uint32_t)(v >> 32);
+  }
+}
+
+template <int TC>
+__global__ __launch_bounds__(kBitsThreads, TC <= 1280 ? 3 : 2) void sim_bits_kernel(SimArgs a) {
+  __shared__ BitsLds<TC> L;
+  constexpr uint32_t NS = 2 * TC;
+  constexpr int kTpt = (TC + kBitsThreads - 1) / kBitsThreads;  // staged tokens per thread
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  uint64_t *const comb_s = L.d.fin;                  // summed m_s, lane = row
+  uint64_t *const fin_s = L.d.fin + kBitsWide * 64;  // m_s, lane = sentence
+  uint64_t *const fin_t = L.d.fin + 2 * kBitsWide * 64;
+
+  for (int64_t item = blockIdx.x; item < a.n_items; item += gridDim.x) {
+    const SimItem it = a.items[item];
+    const int n = it.n, m = it.m;
+    if (m <= 0 || it.i1 <= it.i0) continue;
+    const int64_t *toffs = a.tgt_sent_off + it.tgt_sent0;
+    const int64_t *soffs = a.src_sent_off + it.src_sent0;
+    for (int r0 = it.i0; r0 < it.i1; r0 += 64) {  // the item's strips (items start on a strip)
+      const int R = min(64, n - r0);
+      float *const strip = a.S + it.s_off + (int64_t)(r0 >> 6) * (m + 63) * 64;
+      // this lane's row (every wave holds the strip's rows in the same lanes)
+      int64_t sb = 0;
+      int al = 0;
+      if (lane < R) {
+        sb = clamp64(soffs[r0 + lane], 0, a.n_src_tok);
+        al = (int)min(clamp64(soffs[r0 + lane + 1], sb, a.n_src_tok) - sb, (int64_t)0x7fffffff);
+      }
+      const int amax = __builtin_amdgcn_readfirstlane(wave_max(al));
+
+      for (int j0 = 0; j0 < m;) {
+        // ---- stage the chunk: ids -> local ids, sentences, D ----
+        if (tid < 64) bits_chunk_end<TC>(toffs, j0, m, a.n_tgt_tok, &L.j1, L.ends);
+        if (tid == 0) L.nlid = 0;
+        for (int s = tid; s < (int)NS; s += kBitsThreads) L.h.ent[s] = make_int2(kEmpty, 0);
+        for (int s = tid; s < TC + 2; s += kBitsThreads) L.d.db.D[s] = 0, L.d.db.B[s] = 0;
+        __syncthreads();
+        const int j1 = L.j1, nj = j1 - j0;
+        const int64_t tbase = clamp64(toffs[j0], 0, a.n_tgt_tok);
+        const int ntok = min(L.ends[nj - 1], TC);
+        int32_t xs[kTpt];
+#pragma unroll
+        for (int u = 0; u < kTpt; u++) {
+          const int p = tid + kBitsThreads * u;
+          xs[u] = p < ntok ? a.tgt_tok[tbase + p] : -1;
+        }
+        if (tid < 64) {  // sentence layout by one wave-wide scan
+          int ostart = 0, blen = 0;
+          if (lane < nj) {
+            ostart = lane == 0 ? 0 : min(L.ends[lane - 1], ntok);
+            blen = min(max(L.ends[lane], ostart), ntok) - ostart;
+          }
+          const int plen = (blen + 3) & ~3;
+          int x = plen;
+#pragma unroll
+          for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(x, o);
+            if (lane >= o) x += y;
+          }
+          const int pstart = x - plen;
+          if (lane < nj) {
+            L.toff_o[lane] = (uint16_t)ostart;
+            L.tlen[lane] = (uint16_t)blen;
+            L.toff[lane] = (uint16_t)pstart;
+            for (int q = blen; q < plen; q++) L.tdoc[pstart + q] = 0xFFFF;
+          }
+          if (lane == 0) L.toff_o[nj] = (uint16_t)ntok;
+          if (lane == 63) L.npad = x;
+          const int bm = wave_max(blen);
+          if (lane == 0) L.bmax = bm;
+        }
+        __syncthreads();
+        // every token into the hash; a key new to the chunk takes the next local id
+#pragma unroll
+        for (int u = 0; u < kTpt; u++) {
+          const int p = tid + kBitsThreads * u;
+          bool fresh = false;
+          int h = 0xFFFF;
+          if (p < ntok) {
+            int lo = 0;  // sentence holding token p: the last start <= p
+#pragma unroll
+            for (int step = kJcap / 2; step >= 1; step >>= 1)
+              if (lo + step < nj && L.toff_o[lo + step] <= p) lo += step;
+            const int dst = L.toff[lo] + (p - L.toff_o[lo]);
+            if (xs[u] >= 0) h = bits_insert(L.h.ent, NS, xs[u], fresh);
+            L.tdoc[dst] = (uint16_t)h;
+            L.tsen[dst] = (uint8_t)lo;
+          }
+          const uint64_t nb = __ballot(fresh);
+          if (nb) {
+            const int lead = __builtin_ctzll(nb);
+            int base = 0;
+            if (lane == lead) base = atomicAdd(&L.nlid, __popcll(nb));
+            base = __builtin_amdgcn_readlane(base, lead);
+            if (fresh) L.h.ent[h].y = 1 + base + __popcll(nb & ((1ull << lane) - 1));
+          }
+        }
+        __syncthreads();
+        const int npad = L.npad;
+        for (int q = tid; q < npad; q += kBitsThreads) {
+          const uint16_t s = L.tdoc[q];
+          const int id = s == 0xFFFF ? 0 : L.h.ent[s].y;
+          L.tdoc[q] = (uint16_t)id;
+          if (id) atomicOr(reinterpret_cast<unsigned long long *>(&L.d.db.D[id]), 1ull << L.tsen[q]);
+        }
+        __syncthreads();
+
+        const int jj = lane;  // this lane's sentence in the scoring stage
+        const bool jok = jj < nj;
+        const int bj = jok ? L.tlen[jj] : 0;
+        const int c = j0 + jj;
+        const bool narrow = amax < 64 && L.bmax < 64;
+        if (narrow) {
+          uint32_t slo[kBitsNarrow] = {}, shi[kBitsNarrow] = {}, tlo[kBitsNarrow] = {}, thi[kBitsNarrow] = {};
+          bits_s_pass<kBitsNarrow>(a, L, sb, al, amax, wv, kBitsWaves, slo, shi);
+          __syncthreads();  // B complete; the hash is no longer read
+          uint64_t *xs_s = L.h.xch, *xs_t = L.h.xch + (kBitsWaves - 1) * kBitsNarrow * 64;
+          if (wv > 0) bits_store<kBitsNarrow>(xs_s + (wv - 1) * kBitsNarrow * 64, slo, shi);
+          bits_t_pass<kBitsNarrow>(L, nj, 4 * wv, 4 * kBitsWaves, tlo, thi);
+          if (wv != 1) bits_store<kBitsNarrow>(xs_t + (wv == 0 ? 0 : wv - 1) * kBitsNarrow * 64, tlo, thi);
+          __syncthreads();  // partial counters in place; D and B no longer read
+          if (wv == 0) {
+            for (int w = 0; w < kBitsWaves - 1; w++) {
+              uint32_t ql[kBitsNarrow], qh[kBitsNarrow];
+              bits_load<kBitsNarrow>(xs_s + w * kBitsNarrow * 64, ql, qh);
+              bits_add_counters<kBitsNarrow>(slo, ql);
+              bits_add_counters<kBitsNarrow>(shi, qh);
+            }
+            bits_store<kBitsNarrow>(comb_s, slo, shi);
+          } else if (wv == 1) {
+            for (int w = 0; w < kBitsWaves - 1; w++) {
+              uint32_t ql[kBitsNarrow], qh[kBitsNarrow];
+              bits_load<kBitsNarrow>(xs_t + w * kBitsNarrow * 64, ql, qh);
+              bits_add_counters<kBitsNarrow>(tlo, ql);
+              bits_add_counters<kBitsNarrow>(thi, qh);
+            }
+            bits_store<kBitsNarrow>(fin_t, tlo, thi);
+          }
+          __syncthreads();
+          // transpose m_s: wave w takes planes w and w + 4
+          for (int p = wv; p < kBitsNarrow; p += kBitsWaves) {
+            const uint64_t v = comb_s[p * 64 + lane];
+            uint32_t vl = (uint32_t)v, vh = (uint32_t)(v >> 32);
+            transpose64(vl, vh, lane);
+            fin_s[p * 64 + lane] = ((uint64_t)vh << 32) | vl;
+          }
+          __syncthreads();
+          // score: wave w takes rows 32 h + l0 + 8 k with l0 = 2 w, 2 w + 1
+          uint32_t sl[kBitsNarrow], sh[kBitsNarrow], tl[kBitsNarrow], th[kBitsNarrow];
+          bits_load<kBitsNarrow>(fin_s, sl, sh);
+          bits_load<kBitsNarrow>(fin_t, tl, th);
+          const int tb = bj << (2 * kLogTabLen);
+#pragma unroll
+          for (int h = 0; h < 2; h++) {
+            if (32 * h >= R) break;
+#pragma unroll
+            for (int l1 = 0; l1 < 2; l1++) {
+              const int l0 = 2 * wv + l1;
+              uint32_t ms4 = 0, mt4 = 0;
+#pragma unroll
+              for (int p = 0; p < kBitsNarrow; p++) {
+                ms4 |= (((h ? sh[p] : sl[p]) >> l0) & 0x01010101u) << p;
+                mt4 |= (((h ? th[p] : tl[p]) >> l0) & 0x01010101u) << p;
+              }
+              float sv[4];
+              int pos[4];
+              bool ok[4];
+#pragma unroll
+              for (int k = 0; k < 4; k++) {
+                const int r = 32 * h + l0 + 8 * k;
+                ok[k] = jok && r < R;
+                const int ar = __builtin_amdgcn_readlane(al, r);  // wave-uniform row
+                const uint32_t ms = (ms4 >> (8 * k)) & 0xFFu, mt = (mt4 >> (8 * k)) & 0xFFu;
+                const int idx = (ar << (3 * kLogTabLen)) | tb | (int)(ms << kLogTabLen) | (int)mt;
+                sv[k] = ok[k] ? a.table[idx] : 0.0f;
+                pos[k] = (r + c) * R + r;
+                if (ok[k] && a.ms_out) {
+                  const int64_t cell = it.rm_off + (int64_t)(r0 + r) * m + c;
+                  a.ms_out[cell] = (int32_t)ms;
+                  a.mt_out[cell] = (int32_t)mt;
+                }
+              }
+#pragma unroll
+              for (int k = 0; k < 4; k++)
+                if (ok[k]) strip[pos[k]] = sv[k];
+            }
+          }
+        } else {
+          // sentences of more than 63 tokens: one wave counts, in 11 planes
+          if (wv == 0) {
+            uint32_t slo[kBitsWide] = {}, shi[kBitsWide] = {}, tlo[kBitsWide] = {}, thi[kBitsWide] = {};
+            bits_s_pass<kBitsWide>(a, L, sb, al, amax, 0, 1, slo, shi);
+            wave_sync();
+            bits_t_pass<kBitsWide>(L, nj, 0, 4, tlo, thi);
+#pragma unroll
+            for (int p = 0; p < kBitsWide; p++) transpose64(slo[p], shi[p], lane);
+            wave_sync();  // D and B reads done before the region is overwritten
+            bits_store<kBitsWide>(fin_s, slo, shi);
+            bits_store<kBitsWide>(fin_t, tlo, thi);
+          }
+          __syncthreads();
+          uint32_t sl[kBitsWide], sh[kBitsWide], tl[kBitsWide], th[kBitsWide];
+          bits_load<kBitsWide>(fin_s, sl, sh);
+          bits_load<kBitsWide>(fin_t, tl, th);
+          for (int r = wv; r < R; r += kBitsWaves) {
+            uint32_t ms = 0, mt = 0;
+#pragma unroll
+            for (int p = 0; p < kBitsWide; p++) {
+              ms |= (((r < 32 ? sl[p] >> r : sh[p] >> (r - 32))) & 1u) << p;
+              mt |= (((r < 32 ? tl[p] >> r : th[p] >> (r - 32))) & 1u) << p;
+            }
+            const int ar = __builtin_amdgcn_readlane(al, r);
+            if (jok) {
+              const float sv = (ar < kTabLen && bj < kTabLen)
+                                   ? a.table[(ar << (3 * kLogTabLen)) | (bj << (2 * kLogTabLen)) | (int)(ms << kLogTabLen) | (int)mt]
+                                   : score_direct(a.w0, a.w1, a.w2, a.w3, (int)ms, ar, (int)mt, bj);
+              strip[(r + c) * R + r] = sv;
+              if (a.ms_out) {
+                const int64_t cell = it.rm_off + (int64_t)(r0 + r) * m + c;
+                a.ms_out[cell] = (int32_t)ms;
+                a.mt_out[cell] = (int32_t)mt;
+              }
+            }
+          }
+        }
+        __syncthreads();  // the chunk's LDS is reused by the next one
+        j0 = j1;
+      }
+    }
+  }
+}
+
 // Row-major <-> strip-diagonal copies of whole score blocks (parity entries).
 __global__ __launch_bounds__(256) void relayout_kernel(const PairDesc *descs, int64_t n_pairs, const float *src,
                                                        float *dst, int to_diag) {
@@ -2169,6 +2670,10 @@ hipError_t launch_similarity(const SimArgs &a, int grid, int variant, hipStream_
   if (a.n_items <= 0) return hipSuccess;
   if (variant == 0)
     hipLaunchKernelGGL(sim_tile_kernel, dim3(grid), dim3(kTileThreads), 0, st, a);
+  else if (variant == 3)
+    hipLaunchKernelGGL(sim_bits_kernel<1280>, dim3(grid), dim3(kBitsThreads), 0, st, a);
+  else if (variant == 4)
+    hipLaunchKernelGGL(sim_bits_kernel<2048>, dim3(grid), dim3(kBitsThreads), 0, st, a);
   else if (variant == 2)
     hipLaunchKernelGGL(sim_kernel<true>, dim3(grid), dim3(kSimThreads), 0, st, a);
   else

@@ -326,7 +326,12 @@ ym_status ym_create(int device, size_t hbm_budget_bytes, ym_ctx **out) {
   c->device = device;
   {
     const char *v = getenv("YM_SIM_KERNEL");
-    c->sim_variant = !v ? 1 : std::strcmp(v, "tile") == 0 ? 0 : std::strcmp(v, "split") == 0 ? 2 : 1;
+    c->sim_variant = !v                              ? 1
+                     : std::strcmp(v, "tile") == 0   ? 0
+                     : std::strcmp(v, "split") == 0  ? 2
+                     : std::strcmp(v, "bits") == 0   ? 3
+                     : std::strcmp(v, "bits2k") == 0 ? 4
+                                                     : 1;
   }
   if ((e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking)) != hipSuccess) {
     delete c;

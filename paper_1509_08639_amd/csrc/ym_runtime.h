@@ -120,7 +120,8 @@ struct ym_ctx {
   bool table_valid = false;
   // launch configuration (ym_set_tuning / ym_autotune; read when work is enqueued)
   int sim_variant = 1;  // similarity kernel: 1 lane per target sentence (default), 2 the same with reads of long
-                        // sentences split over spare lanes (YM_SIM_KERNEL=split), 0 bit-sliced tiles (=tile)
+                        // sentences split over spare lanes (YM_SIM_KERNEL=split), 0 bit-sliced tiles (=tile),
+                        // 3 / 4 bit-sliced tiles of four waves, 1,280- / 2,048-token chunks (=bits / =bits2k)
   int item_rows = ym::kItemRows;  // source sentences per similarity work item
   int nw_pairs_per_group = 1;     // NW workgroup size in pairs (one wave each)
   uint64_t nw_wait_ticks = ym::kNwWaitTicks;  // limit of one bounded wait of the pipelined sweep

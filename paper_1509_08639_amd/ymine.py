@@ -35,6 +35,7 @@ EXPORTS = [
     "ym_profile_enable", "ym_profile_read", "ym_server_start", "ym_submit", "ym_poll", "ym_server_next_done", "ym_cancel",
     "ym_server_stop",
     "ym_server_stats", "ym_server_graph_stats", "ym_check_pair", "ym_set_wait_limit", "ym_mine_device_static",
+    "ym_tune_select",
 ]
 
 
@@ -334,6 +335,25 @@ def tune(ctx: Context, lex: Lexicon, corpus, w, gaps, taus, truth_off, truth_src
     return nm.reshape(len(gaps), len(taus)), nc.reshape(len(gaps), len(taus))
 
 
+class TuneChoice(C.Structure):
+    _fields_ = [("gap_index", i32), ("tau_index", i32), ("n_mined", i64), ("n_correct", i64),
+                ("precision", C.c_double), ("recall", C.c_double), ("f1", C.c_double)]
+
+
+def tune_select(n_mined, n_correct, n_truth: int) -> dict:
+    """ym_tune_select: the sweep entry (gap index, threshold index) with the
+    highest F1 against n_truth reference pairs, and its figures."""
+    nm2 = np.atleast_2d(np.asarray(n_mined, np.int64))
+    nc2 = np.atleast_2d(np.asarray(n_correct, np.int64))
+    if nm2.shape != nc2.shape or nm2.ndim != 2:
+        raise ValueError("n_mined and n_correct must be [n_gaps, n_taus] arrays of one shape")
+    nm, nc = _c(nm2, np.int64), _c(nc2, np.int64)
+    out = TuneChoice()
+    _check(lib().ym_tune_select(_ptr(nm, i64), _ptr(nc, i64), nm2.shape[0], nm2.shape[1], int(n_truth), C.byref(out)))
+    return dict(gap_index=out.gap_index, tau_index=out.tau_index, n_mined=out.n_mined, n_correct=out.n_correct,
+                precision=out.precision, recall=out.recall, f1=out.f1)
+
+
 def mine_bidirectional(ctx: Context, lex_fwd: Lexicon, lex_rev: Lexicon, corpus, w_fwd, w_rev, gap, threshold) -> dict:
     """ym_mine_bidirectional: union of forward and reverse mining per pair."""
     hb = _HostBatch(corpus)
@@ -357,8 +377,10 @@ def set_wait_limit(ctx: Context, ticks: int) -> None:
 
 def set_tuning(ctx: Context, sim_kernel: int, item_rows: int, nw_pairs_per_group: int):
     """ym_set_tuning: similarity kernel (1 lanes, 2 lanes with split reads of
-    long target sentences, 0 bit-sliced tiles), source rows per work item (64,
-    128, 256), NW pairs per workgroup (1, 2, 4).  No choice changes a result."""
+    long target sentences, 0 bit-sliced tiles of one wave, 3 / 4 bit-sliced
+    tiles of four waves with chunks of 1,280 / 2,048 tokens), source rows per
+    work item (64, 128, 256), NW pairs per workgroup (1, 2, 4).  No choice
+    changes a result."""
     t = Tuning(sim_kernel, item_rows, nw_pairs_per_group)
     _check(lib().ym_set_tuning(ctx.h, C.byref(t)))
 

@@ -32,12 +32,19 @@ def ctx(ym):
 
 
 @pytest.fixture(scope="module")
-def ctx_split(ym):
-    """A context whose similarity kernel splits the reads of target sentences
-    longer than 32 tokens over spare lanes (kernel 2)."""
-    c = ym.Context(0)
-    ym.set_tuning(c, 2, 128, 1)
-    return c
+def ctx_k(ym, ctx):
+    """Contexts by similarity kernel: 1 (the default context), 2 (reads of
+    target sentences longer than 32 tokens split over spare lanes), 3 and 4
+    (bit-sliced tiles of four waves, 1,280- and 2,048-token chunks)."""
+    made = {1: ctx}
+
+    def get(k):
+        if k not in made:
+            c = ym.Context(0)
+            ym.set_tuning(c, k, 128, 1)
+            made[k] = c
+        return made[k]
+    return get
 
 
 @pytest.fixture(scope="module")
@@ -71,25 +78,25 @@ def test_similarity_single_pair(ym, ctx, O):
     _similarity_check(ym, ctx, O, lex, c, synth.weights(cfg.seed))
 
 
-@pytest.mark.parametrize("seed,split", [(1, False), (2, False), (3, False), (1, True), (2, True)])
-def test_similarity_ragged_edges(ym, ctx, ctx_split, O, seed, split):
+@pytest.mark.parametrize("seed,kernel", [(1, 1), (2, 1), (3, 1), (1, 2), (2, 2), (1, 3), (2, 3), (3, 3), (1, 4), (2, 4)])
+def test_similarity_ragged_edges(ym, ctx_k, O, seed, kernel):
     # empty documents and sentences, negative / unknown ids, source sentences
     # of more than 31 and 63 tokens (one-row path, extra mask passes), > 128 source
     # sentences (several work items), > 256 target sentences (several chunks)
     lex = parity.random_lexicon(seed)
     c = parity.random_corpus(seed, n_pairs=12, nmax=150, mmax=300, lmax_src=70, lmax_tgt=40)
     w = np.array([-2.0, 3.0, 2.5, 0.75], np.float32)
-    _similarity_check(ym, ctx_split if split else ctx, O, lex, c, w)
+    _similarity_check(ym, ctx_k(kernel), O, lex, c, w)
 
 
-@pytest.mark.parametrize("split", [False, True])
-def test_similarity_long_sentences(ym, ctx, ctx_split, O, split):
+@pytest.mark.parametrize("kernel", [1, 2, 3, 4])
+def test_similarity_long_sentences(ym, ctx_k, O, kernel):
     # source sentences of up to 200 tokens (up to four mask passes of 63
     # positions), target sentences of up to 130 (split reads: groups of up to
     # 8 lanes per sentence)
     lex = parity.random_lexicon(4, vocab=300)
     c = parity.random_corpus(4, n_pairs=8, nmax=70, mmax=90, lmax_src=200, lmax_tgt=130, vocab=300)
-    _similarity_check(ym, ctx_split if split else ctx, O, lex, c, np.array([-2.0, 3.0, 2.5, 0.75], np.float32))
+    _similarity_check(ym, ctx_k(kernel), O, lex, c, np.array([-2.0, 3.0, 2.5, 0.75], np.float32))
 
 
 def test_similarity_key_ids_beyond_dense_table(ym, ctx, O):
@@ -105,18 +112,22 @@ def test_similarity_key_ids_beyond_dense_table(ym, ctx, O):
     _similarity_check(ym, ctx, O, lex2, c, np.array([-2.0, 3.0, 2.5, 0.75], np.float32))
 
 
-@pytest.mark.parametrize("split", [False, True])
-def test_similarity_chunk_boundaries(ym, ctx, ctx_split, O, split):
-    # target sentences near the 1024-token chunk limit and many short ones
+@pytest.mark.parametrize("kernel", [1, 2, 3, 4])
+def test_similarity_chunk_boundaries(ym, ctx_k, O, kernel):
+    # target sentences near the chunk limits (1,024, 1,280 and 2,048 tokens)
+    # and many short ones
     lex = parity.random_lexicon(9, vocab=400)
     r = np.random.default_rng(9)
     srcs = [[r.integers(0, 400, int(r.integers(1, 40))).astype(np.int32) for _ in range(7)]]
     tgts = [[r.integers(0, 400, L).astype(np.int32) for L in (1024, 1, 1023, 2, 600, 500, 0, 1024)]]
     srcs.append([r.integers(0, 400, 5).astype(np.int32) for _ in range(3)])
     tgts.append([r.integers(0, 400, 3).astype(np.int32) for _ in range(700)])
+    srcs.append([r.integers(0, 400, int(r.integers(1, 60))).astype(np.int32) for _ in range(70)])
+    tgts.append([r.integers(0, 400, L).astype(np.int32)
+                 for L in (640, 640, 1, 700, 579, 1, 1024, 1024, 0, 3, 1024, 255, 1, 1, 1000, 47) + (60,) * 40])
     c = synth.from_lists(srcs, tgts)
     # one-sentence chunks of 1,024 tokens: with split reads, groups of all 64 lanes
-    _similarity_check(ym, ctx_split if split else ctx, O, lex, c, np.array([-1.0, 2.0, 2.0, 0.5], np.float32))
+    _similarity_check(ym, ctx_k(kernel), O, lex, c, np.array([-1.0, 2.0, 2.0, 0.5], np.float32))
 
 
 def _nw_cases():
@@ -303,15 +314,15 @@ def test_errors(ym, ctx):
 
 @pytest.mark.parametrize("seed", [5, 6])
 def test_similarity_variants_agree(ym, O, seed):
-    """The bit-sliced tile kernel and the lane-per-sentence kernel, with and
-    without split reads, give the same counts and scores (all also match the
-    oracle above)."""
+    """The bit-sliced tile kernels (one wave, four waves with both chunk
+    sizes) and the lane-per-sentence kernel, with and without split reads,
+    give the same counts and scores (all also match the oracle above)."""
     import os
     lex = parity.random_lexicon(seed, vocab=90)
     c = parity.random_corpus(seed, n_pairs=10, nmax=140, mmax=150, lmax_src=70, lmax_tgt=66)
     w = np.array([-2.0, 3.0, 2.5, 0.75], np.float32)
     outs = []
-    for variant in ("tile", "lanes", "split"):
+    for variant in ("tile", "lanes", "split", "bits", "bits2k"):
         old = os.environ.get("YM_SIM_KERNEL")
         os.environ["YM_SIM_KERNEL"] = variant
         try:
@@ -330,13 +341,13 @@ def test_similarity_variants_agree(ym, O, seed):
             assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("split", [False, True])
-def test_scale_workload_sample(ym, ctx, ctx_split, O, split):
+@pytest.mark.parametrize("kernel", [1, 2, 3, 4])
+def test_scale_workload_sample(ym, ctx_k, O, kernel):
     """Pairs of the 1M-pair scale workload (3-60 token sentences, Zipf 1.05,
     1-4 translations per key): rows longer than 31 tokens take the one-row
     path, target sentences longer than 32 tokens the split reads (kernel 2);
     the mined sets match the oracle."""
-    ctx = ctx_split if split else ctx
+    ctx = ctx_k(kernel)
     cfg = synth.CONFIGS[4]
     lex = synth.make_lexicon(cfg)
     c = synth.generate(cfg, lex, pair_ids=np.arange(0, 1000000, 20000))

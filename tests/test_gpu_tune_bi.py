@@ -5,6 +5,8 @@ gap penalty with every diagonal move kept and counts, per threshold, accepted
 and reference pairs; bidirectional mining joins a forward run with a run on
 the swapped batch.  The oracle side composes the oracle miner the same way.
 """
+from fractions import Fraction
+
 import numpy as np
 import pytest
 
@@ -87,6 +89,22 @@ def test_tune_matches_oracle_sweep(ym, ctx, O):
     # precision rises with the threshold; counts never exceed the reference size
     assert np.all(nc <= nm) and np.all(np.diff(nm, axis=1) <= 0)
     assert np.all(nc <= int(c.truth_off[-1]))
+    # the chosen (gap, threshold) is the oracle sweep's F1 argmax (exact
+    # rationals, first entry on ties)
+    truth = int(c.truth_off[-1])
+    om_all = np.zeros_like(nm)
+    oc_all = np.zeros_like(nc)
+    for gi, g in enumerate(gaps):
+        om_all[gi], oc_all[gi] = _counts(O.mine(OL, c, w, g, F32(-1.0)), c, taus)
+    best = None
+    for gi in range(len(gaps)):
+        for ti in range(len(taus)):
+            f = Fraction(2 * int(oc_all[gi, ti]), int(om_all[gi, ti]) + truth)
+            if best is None or f > best[0]:
+                best = (f, gi, ti)
+    choice = ym.tune_select(nm, nc, truth)
+    assert (choice["gap_index"], choice["tau_index"]) == best[1:]
+    assert choice["f1"] == pytest.approx(float(best[0]), rel=1e-15, abs=0.0)
 
 
 def test_tune_small_workspace_and_edges(ym, ctx, O):

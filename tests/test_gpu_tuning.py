@@ -14,7 +14,7 @@ from . import parity
 pytestmark = pytest.mark.gpu
 
 F32 = np.float32
-CONFIGS = list(itertools.product([1, 2, 0], [64, 128, 256], [1, 2, 4]))
+CONFIGS = list(itertools.product([1, 2, 0, 3, 4], [64, 128, 256], [1, 2, 4]))
 
 
 @pytest.fixture(scope="module")
@@ -61,7 +61,7 @@ def test_every_configuration_gives_the_same_result(ym):
 
 def test_set_tuning_rejects_other_values(ym):
     ctx = ym.Context(0)
-    for bad in [(3, 128, 1), (-1, 128, 1), (1, 96, 1), (1, 512, 1), (1, 128, 3), (0, 128, 8)]:
+    for bad in [(5, 128, 1), (-1, 128, 1), (1, 96, 1), (1, 512, 1), (1, 128, 3), (0, 128, 8)]:
         with pytest.raises(ym.YmError):
             ym.set_tuning(ctx, *bad)
     assert ym.get_tuning(ctx) == dict(sim_kernel=1, item_rows=128, nw_pairs_per_group=1)
