@@ -1518,10 +1518,10 @@ constexpr int kBitsWide = 11;   // planes for counts <= 2047 (sentences of at mo
 
 template <int TC>
 struct BitsLds {
-  // region H: the chunk's id hash {key, local id}; once the source pass is
-  // done, the partial counters of the waves
+  // region H: the chunk's id hash (TC buckets of two {key, local id} slots);
+  // once the source pass is done, the partial counters of the waves
   union {
-    int2 ent[2 * TC];
+    __align__(16) int2 ent[2 * TC];
     uint64_t xch[2 * (kBitsWaves - 1) * kBitsNarrow * 64];
   } h;
   // region DB: D and B (id 0: none, always 0; id TC + 1: where lookups that
@@ -1541,53 +1541,58 @@ struct BitsLds {
   int j1, nlid, npad, bmax;
 };
 
-__device__ __forceinline__ uint32_t bits_slot(int32_t x, uint32_t ns) { return __umulhi(hash32(x), ns); }
+// The chunk's id hash: NB buckets of two {key, local id} slots, read with one
+// 16-byte load.  A key goes to the first free slot from its home bucket on
+// (slot 0 before slot 1, then the next bucket), so a bucket whose slot 1 is
+// free ends every search.
+__device__ __forceinline__ uint32_t bits_bucket(int32_t x, uint32_t nb) { return __umulhi(hash32(x), nb); }
 
-// Insert target id x (>= 0) into a hash of ns slots: its slot, and whether x was new.
-__device__ __forceinline__ int bits_insert(int2 *ent, uint32_t ns, int32_t x, bool &fresh) {
-  uint32_t h = bits_slot(x, ns);
+// Insert target id x (>= 0): its slot (2 bucket + 0 or 1), and whether x was new.
+__device__ __forceinline__ int bits_insert(int2 *ent, uint32_t nb, int32_t x, bool &fresh) {
+  uint32_t b = bits_bucket(x, nb);
   for (;;) {  // at most TC distinct keys in 2 TC slots
-    const int prev = atomicCAS(&ent[h].x, kEmpty, x);
-    if (prev == kEmpty || prev == x) {
-      fresh = prev == kEmpty;
-      return (int)h;
+#pragma unroll
+    for (int k = 0; k < 2; k++) {
+      const int prev = atomicCAS(&ent[2 * b + k].x, kEmpty, x);
+      if (prev == kEmpty || prev == x) {
+        fresh = prev == kEmpty;
+        return (int)(2 * b + k);
+      }
     }
-    h = h + 1 == ns ? 0 : h + 1;
+    b = b + 1 == nb ? 0 : b + 1;
   }
 }
 
-// Local ids of K target ids at once (0: not an id of the chunk, or x < 0):
-// every first probe is issued before any second one.
+// Local ids of K target ids at once (0: not an id of the chunk, or x < 0).
+// Every home bucket is read before any further one; the rare searches that go
+// on are tracked in one bit mask per lane.
 template <int K>
-__device__ __forceinline__ void bits_find(const int2 *ent, uint32_t ns, const int32_t (&x)[K], int (&lid)[K]) {
-  uint32_t h[K];
-  int2 e[K];
-  bool p[K];
+__device__ __forceinline__ void bits_find(const int4 *ent4, uint32_t nb, const int32_t (&x)[K], int (&lid)[K]) {
+  static_assert(K <= 32, "pending searches are one bit each");
+  uint32_t b[K];
+  int4 e[K];
 #pragma unroll
   for (int k = 0; k < K; k++) {
-    h[k] = bits_slot(x[k], ns);
-    e[k] = ent[h[k]];
+    b[k] = bits_bucket(x[k], nb);
+    e[k] = ent4[b[k]];
   }
-  bool any = false;
+  uint32_t pend = 0;
 #pragma unroll
   for (int k = 0; k < K; k++) {
-    p[k] = x[k] >= 0 && e[k].x != x[k] && e[k].x != kEmpty;
-    any |= p[k];
+    lid[k] = (x[k] >= 0 && e[k].x == x[k]) ? e[k].y : (x[k] >= 0 && e[k].z == x[k]) ? e[k].w : 0;
+    pend |= (uint32_t)(x[k] >= 0 && lid[k] == 0 && e[k].z != kEmpty) << k;
   }
-  while (any) {
-    any = false;
+  while (pend) {
 #pragma unroll
     for (int k = 0; k < K; k++) {
-      if (p[k]) {
-        h[k] = h[k] + 1 == ns ? 0 : h[k] + 1;
-        e[k] = ent[h[k]];
-        p[k] = e[k].x != x[k] && e[k].x != kEmpty;
-        any |= p[k];
+      if ((pend >> k) & 1u) {
+        b[k] = b[k] + 1 == nb ? 0 : b[k] + 1;
+        const int4 f = ent4[b[k]];
+        lid[k] = f.x == x[k] ? f.y : f.z == x[k] ? f.w : 0;
+        if (lid[k] != 0 || f.z == kEmpty) pend &= ~(1u << k);
       }
     }
   }
-#pragma unroll
-  for (int k = 0; k < K; k++) lid[k] = (x[k] >= 0 && e[k].x == x[k]) ? e[k].y : 0;
 }
 
 // Carry-save adder: a + b + c = s + 2 carry, bit by bit.
@@ -1650,7 +1655,8 @@ __device__ __forceinline__ void bits_chunk_end(const int64_t *toffs, int j0, int
 template <int NPL, int TC>
 __device__ __forceinline__ void bits_s_pass(const SimArgs &a, BitsLds<TC> &L, int64_t sb, int al, int amax, int q0,
                                             int qs, uint32_t (&lo)[NPL], uint32_t (&hi)[NPL]) {
-  constexpr uint32_t NS = 2 * TC;
+  constexpr uint32_t NB = TC;  // buckets of two slots
+  const int4 *ent4 = reinterpret_cast<const int4 *>(L.h.ent);
   const int lane = threadIdx.x & 63;
   const unsigned long long rowbit = 1ull << lane;
   unsigned long long *B = reinterpret_cast<unsigned long long *>(L.d.db.B);
@@ -1667,24 +1673,29 @@ __device__ __forceinline__ void bits_s_pass(const SimArgs &a, BitsLds<TC> &L, in
   for (int u = 0; q0 + qs * 4 * u < amax; u++) {
     int4 rb[4];
     fetch(u + 1, rb);
-    int32_t x[16];
     bool far = false;
-#pragma unroll
-    for (int k = 0; k < 4; k++) {
-      const bool f = ra[k].x == -2;  // more than four translations: looked up below
-      far |= f;
-      x[4 * k] = f ? -1 : ra[k].x;
-      x[4 * k + 1] = f ? -1 : ra[k].y;
-      x[4 * k + 2] = f ? -1 : ra[k].z;
-      x[4 * k + 3] = f ? -1 : ra[k].w;
-    }
-    int lid[16];
-    bits_find<16>(L.h.ent, NS, x, lid);
-#pragma unroll
-    for (int k = 0; k < 16; k++) atomicOr(&B[lid[k] ? lid[k] : TC + 1], rowbit);
     uint64_t c[4];
 #pragma unroll
-    for (int k = 0; k < 4; k++) c[k] = (D[lid[4 * k]] | D[lid[4 * k + 1]]) | (D[lid[4 * k + 2]] | D[lid[4 * k + 3]]);
+    for (int hf = 0; hf < 2; hf++) {  // two records at a time (register pressure)
+      int32_t x[8];
+#pragma unroll
+      for (int k = 0; k < 2; k++) {
+        const int4 rr = ra[2 * hf + k];
+        const bool f = rr.x == -2;  // more than four translations: looked up below
+        far |= f;
+        x[4 * k] = f ? -1 : rr.x;
+        x[4 * k + 1] = f ? -1 : rr.y;
+        x[4 * k + 2] = f ? -1 : rr.z;
+        x[4 * k + 3] = f ? -1 : rr.w;
+      }
+      int lid[8];
+      bits_find<8>(ent4, NB, x, lid);
+#pragma unroll
+      for (int k = 0; k < 8; k++) atomicOr(&B[lid[k] ? lid[k] : TC + 1], rowbit);
+#pragma unroll
+      for (int k = 0; k < 2; k++)
+        c[2 * hf + k] = (D[lid[4 * k]] | D[lid[4 * k + 1]]) | (D[lid[4 * k + 2]] | D[lid[4 * k + 3]]);
+    }
     if (far) {
 #pragma unroll
       for (int k = 0; k < 4; k++) {
@@ -1692,7 +1703,7 @@ __device__ __forceinline__ void bits_s_pass(const SimArgs &a, BitsLds<TC> &L, in
           for (int e = 0; e < ra[k].z; e++) {
             const int32_t y[1] = {a.lex.vals[ra[k].y + e]};
             int l[1];
-            bits_find<1>(L.h.ent, NS, y, l);
+            bits_find<1>(ent4, NB, y, l);
             atomicOr(&B[l[0] ? l[0] : TC + 1], rowbit);
             c[k] |= D[l[0]];
           }
@@ -1736,6 +1747,47 @@ __device__ __forceinline__ void bits_t_pass(const BitsLds<TC> &L, int nj, int k0
       bits_add4<NPL>(hi, (uint32_t)(x[4 * g] >> 32), (uint32_t)(x[4 * g + 1] >> 32), (uint32_t)(x[4 * g + 2] >> 32),
                      (uint32_t)(x[4 * g + 3] >> 32));
     }
+  }
+}
+
+// Transpose a 64 x 64 bit matrix held one row per lane (lo: columns 0-31,
+// hi: 32-63); afterwards lane c holds column c.  The six exchange stages use
+// lane moves that stay in the VALU: the lane-half swap for distance 32, the
+// row-pair swap for 16, and DPP mirrors and quad permutes for 8, 4, 2, 1.
+__device__ __forceinline__ uint32_t bits_xor_lane(uint32_t v, int d) {
+  switch (d) {
+    case 1: return dpp_mov<0xB1>(v);                  // quad_perm [1, 0, 3, 2]
+    case 2: return dpp_mov<0x4E>(v);                  // quad_perm [2, 3, 0, 1]
+    case 4: return dpp_mov<0x1B>(dpp_mov<0x141>(v));  // half-row mirror, then quad_perm [3, 2, 1, 0]
+    default: return dpp_mov<0x141>(dpp_mov<0x140>(v));  // row mirror, then half-row mirror (distance 8)
+  }
+}
+
+__device__ __forceinline__ void bits_transpose64(uint32_t &lo, uint32_t &hi, int lane) {
+  {  // distance 32: lanes 0-31 take the low words of lanes 32-63 as their high words and vice versa
+    const auto r = __builtin_amdgcn_permlane32_swap(lo, hi, false, false);
+    lo = r[0];
+    hi = r[1];
+  }
+  {  // distance 16 (inside each 32-lane half): the lower lane of a pair swaps its high 16 bits with
+     // the upper lane's low 16 bits
+    const bool up = (lane & 16) != 0;
+    const uint32_t xl = up ? (lo & 0xFFFFu) : (lo >> 16), xh = up ? (hi & 0xFFFFu) : (hi >> 16);
+    const auto rl = __builtin_amdgcn_permlane16_swap(xl, xl, false, false);
+    const auto rh = __builtin_amdgcn_permlane16_swap(xh, xh, false, false);
+    const uint32_t yl = up ? rl[0] : rl[1], yh = up ? rh[0] : rh[1];
+    lo = up ? ((lo & 0xFFFF0000u) | yl) : ((lo & 0xFFFFu) | (yl << 16));
+    hi = up ? ((hi & 0xFFFF0000u) | yh) : ((hi & 0xFFFFu) | (yh << 16));
+  }
+#pragma unroll
+  for (int s = 8; s >= 1; s >>= 1) {
+    const uint32_t m = s == 8 ? 0x00FF00FFu : s == 4 ? 0x0F0F0F0Fu : s == 2 ? 0x33333333u : 0x55555555u;
+    const uint32_t ylo = bits_xor_lane(lo, s), yhi = bits_xor_lane(hi, s);
+    const bool up = (lane & s) != 0;
+    const uint32_t alo = (lo & m) | ((ylo & m) << s), ahi = (hi & m) | ((yhi & m) << s);
+    const uint32_t blo = (lo & ~m) | ((ylo & ~m) >> s), bhi = (hi & ~m) | ((yhi & ~m) >> s);
+    lo = up ? blo : alo;
+    hi = up ? bhi : ahi;
   }
 }
 
@@ -1840,7 +1892,7 @@ __global__ __launch_bounds__(kBitsThreads, TC <= 1280 ? 3 : 2) void sim_bits_ker
             for (int step = kJcap / 2; step >= 1; step >>= 1)
               if (lo + step < nj && L.toff_o[lo + step] <= p) lo += step;
             const int dst = L.toff[lo] + (p - L.toff_o[lo]);
-            if (xs[u] >= 0) h = bits_insert(L.h.ent, NS, xs[u], fresh);
+            if (xs[u] >= 0) h = bits_insert(L.h.ent, (uint32_t)TC, xs[u], fresh);
             L.tdoc[dst] = (uint16_t)h;
             L.tsen[dst] = (uint8_t)lo;
           }
@@ -1899,48 +1951,47 @@ __global__ __launch_bounds__(kBitsThreads, TC <= 1280 ? 3 : 2) void sim_bits_ker
           for (int p = wv; p < kBitsNarrow; p += kBitsWaves) {
             const uint64_t v = comb_s[p * 64 + lane];
             uint32_t vl = (uint32_t)v, vh = (uint32_t)(v >> 32);
-            transpose64(vl, vh, lane);
+            bits_transpose64(vl, vh, lane);
             fin_s[p * 64 + lane] = ((uint64_t)vh << 32) | vl;
           }
           __syncthreads();
-          // score: wave w takes rows 32 h + l0 + 8 k with l0 = 2 w, 2 w + 1
+          // score: wave w takes rows 32 h + l0 + 8 k with l0 = 2 w, 2 w + 1;
+          // all sixteen table reads are issued before the first store
           uint32_t sl[kBitsNarrow], sh[kBitsNarrow], tl[kBitsNarrow], th[kBitsNarrow];
           bits_load<kBitsNarrow>(fin_s, sl, sh);
           bits_load<kBitsNarrow>(fin_t, tl, th);
           const int tb = bj << (2 * kLogTabLen);
+          float sv[16];
 #pragma unroll
-          for (int h = 0; h < 2; h++) {
-            if (32 * h >= R) break;
+          for (int g = 0; g < 4; g++) {
+            const int h = g >> 1, l0 = 2 * wv + (g & 1);
+            uint32_t ms4 = 0, mt4 = 0;
 #pragma unroll
-            for (int l1 = 0; l1 < 2; l1++) {
-              const int l0 = 2 * wv + l1;
-              uint32_t ms4 = 0, mt4 = 0;
+            for (int p = 0; p < kBitsNarrow; p++) {
+              ms4 |= (((h ? sh[p] : sl[p]) >> l0) & 0x01010101u) << p;
+              mt4 |= (((h ? th[p] : tl[p]) >> l0) & 0x01010101u) << p;
+            }
 #pragma unroll
-              for (int p = 0; p < kBitsNarrow; p++) {
-                ms4 |= (((h ? sh[p] : sl[p]) >> l0) & 0x01010101u) << p;
-                mt4 |= (((h ? th[p] : tl[p]) >> l0) & 0x01010101u) << p;
+            for (int k = 0; k < 4; k++) {
+              const int r = 32 * h + l0 + 8 * k;
+              const bool ok = jok && r < R;
+              const int ar = __builtin_amdgcn_readlane(al, r);  // wave-uniform row
+              const uint32_t ms = (ms4 >> (8 * k)) & 0xFFu, mt = (mt4 >> (8 * k)) & 0xFFu;
+              const int idx = (ar << (3 * kLogTabLen)) | tb | (int)(ms << kLogTabLen) | (int)mt;
+              sv[4 * g + k] = ok ? a.table[idx] : 0.0f;
+              if (ok && a.ms_out) {
+                const int64_t cell = it.rm_off + (int64_t)(r0 + r) * m + c;
+                a.ms_out[cell] = (int32_t)ms;
+                a.mt_out[cell] = (int32_t)mt;
               }
-              float sv[4];
-              int pos[4];
-              bool ok[4];
+            }
+          }
 #pragma unroll
-              for (int k = 0; k < 4; k++) {
-                const int r = 32 * h + l0 + 8 * k;
-                ok[k] = jok && r < R;
-                const int ar = __builtin_amdgcn_readlane(al, r);  // wave-uniform row
-                const uint32_t ms = (ms4 >> (8 * k)) & 0xFFu, mt = (mt4 >> (8 * k)) & 0xFFu;
-                const int idx = (ar << (3 * kLogTabLen)) | tb | (int)(ms << kLogTabLen) | (int)mt;
-                sv[k] = ok[k] ? a.table[idx] : 0.0f;
-                pos[k] = (r + c) * R + r;
-                if (ok[k] && a.ms_out) {
-                  const int64_t cell = it.rm_off + (int64_t)(r0 + r) * m + c;
-                  a.ms_out[cell] = (int32_t)ms;
-                  a.mt_out[cell] = (int32_t)mt;
-                }
-              }
+          for (int g = 0; g < 4; g++) {
 #pragma unroll
-              for (int k = 0; k < 4; k++)
-                if (ok[k]) strip[pos[k]] = sv[k];
+            for (int k = 0; k < 4; k++) {
+              const int r = 32 * (g >> 1) + 2 * wv + (g & 1) + 8 * k;
+              if (jok && r < R) strip[(r + c) * R + r] = sv[4 * g + k];
             }
           }
         } else {
@@ -1951,7 +2002,7 @@ __global__ __launch_bounds__(kBitsThreads, TC <= 1280 ? 3 : 2) void sim_bits_ker
             wave_sync();
             bits_t_pass<kBitsWide>(L, nj, 0, 4, tlo, thi);
 #pragma unroll
-            for (int p = 0; p < kBitsWide; p++) transpose64(slo[p], shi[p], lane);
+            for (int p = 0; p < kBitsWide; p++) bits_transpose64(slo[p], shi[p], lane);
             wave_sync();  // D and B reads done before the region is overwritten
             bits_store<kBitsWide>(fin_s, slo, shi);
             bits_store<kBitsWide>(fin_t, tlo, thi);
