@@ -1524,8 +1524,8 @@ struct BitsLds {
     __align__(16) int2 ent[2 * TC];
     uint64_t xch[2 * (kBitsWaves - 1) * kBitsNarrow * 64];
   } h;
-  // region DB: D and B (id 0: none, always 0; id TC + 1: where lookups that
-  // found nothing mark); once the target pass is done, the summed m_s
+  // region DB: D and B (id 0: none, always 0; one spare entry); once the
+  // target pass is done, the summed m_s
   // (row-major), the transposed m_s and m_t (lane = sentence)
   union {
     struct {
@@ -1690,8 +1690,11 @@ __device__ __forceinline__ void bits_s_pass(const SimArgs &a, BitsLds<TC> &L, in
       }
       int lid[8];
       bits_find<8>(ent4, NB, x, lid);
+      // only ids of the chunk are marked (most translations miss it; marking
+      // the misses in one shared slot would serialise the atomics)
 #pragma unroll
-      for (int k = 0; k < 8; k++) atomicOr(&B[lid[k] ? lid[k] : TC + 1], rowbit);
+      for (int k = 0; k < 8; k++)
+        if (lid[k]) atomicOr(&B[lid[k]], rowbit);
 #pragma unroll
       for (int k = 0; k < 2; k++)
         c[2 * hf + k] = (D[lid[4 * k]] | D[lid[4 * k + 1]]) | (D[lid[4 * k + 2]] | D[lid[4 * k + 3]]);
@@ -1704,7 +1707,7 @@ __device__ __forceinline__ void bits_s_pass(const SimArgs &a, BitsLds<TC> &L, in
             const int32_t y[1] = {a.lex.vals[ra[k].y + e]};
             int l[1];
             bits_find<1>(ent4, NB, y, l);
-            atomicOr(&B[l[0] ? l[0] : TC + 1], rowbit);
+            if (l[0]) atomicOr(&B[l[0]], rowbit);
             c[k] |= D[l[0]];
           }
         }
