@@ -1516,12 +1516,18 @@ constexpr int kBitsThreads = 64 * kBitsWaves;
 constexpr int kBitsNarrow = 6;  // planes for counts <= 63
 constexpr int kBitsWide = 11;   // planes for counts <= 2047 (sentences of at most 1024 tokens)
 
+// TC buckets of two slots (load <= 1/2); the bucket of an id is the high
+// word of its multiplicative hash times TC.
+template <int TC>
+struct BitsHash {
+  static constexpr uint32_t kNB = TC;
+};
 template <int TC>
 struct BitsLds {
   // region H: the chunk's id hash (TC buckets of two {key, local id} slots);
   // once the source pass is done, the partial counters of the waves
   union {
-    __align__(16) int2 ent[2 * TC];
+    __align__(16) int2 ent[2 * BitsHash<TC>::kNB];
     uint64_t xch[2 * (kBitsWaves - 1) * kBitsNarrow * 64];
   } h;
   // region DB: D and B (id 0: none, always 0; one spare entry); once the
@@ -1543,13 +1549,20 @@ struct BitsLds {
 
 // The chunk's id hash: NB buckets of two {key, local id} slots, read with one
 // 16-byte load.  A key goes to the first free slot from its home bucket on
-// (slot 0 before slot 1, then the next bucket), so a bucket whose slot 1 is
-// free ends every search.
-__device__ __forceinline__ uint32_t bits_bucket(int32_t x, uint32_t nb) { return __umulhi(hash32(x), nb); }
+// (slot 0 before slot 1, then the next bucket); an insert that finds a bucket
+// full of other keys marks it (kBitsOverflow in slot 1's id word) before
+// moving on.  A search therefore ends at the first bucket that holds its key
+// or carries no mark, which for most searches is the home bucket.
+constexpr int kBitsOverflow = 1 << 30;
+constexpr int kBitsIdMask = 0xFFFF;
+
+template <uint32_t NB>
+__device__ __forceinline__ uint32_t bits_bucket(int32_t x) { return __umulhi(hash32(x), NB); }
 
 // Insert target id x (>= 0): its slot (2 bucket + 0 or 1), and whether x was new.
-__device__ __forceinline__ int bits_insert(int2 *ent, uint32_t nb, int32_t x, bool &fresh) {
-  uint32_t b = bits_bucket(x, nb);
+template <uint32_t NB>
+__device__ __forceinline__ int bits_insert(int2 *ent, int32_t x, bool &fresh) {
+  uint32_t b = bits_bucket<NB>(x);
   for (;;) {  // at most TC distinct keys in 2 TC slots
 #pragma unroll
     for (int k = 0; k < 2; k++) {
@@ -1559,37 +1572,43 @@ __device__ __forceinline__ int bits_insert(int2 *ent, uint32_t nb, int32_t x, bo
         return (int)(2 * b + k);
       }
     }
-    b = b + 1 == nb ? 0 : b + 1;
+    atomicOr(&ent[2 * b + 1].y, kBitsOverflow);  // searches passing this bucket go on
+    b = b + 1 == NB ? 0 : b + 1;
   }
 }
 
 // Local ids of K target ids at once (0: not an id of the chunk, or x < 0).
-// Every home bucket is read before any further one; the rare searches that go
-// on are tracked in one bit mask per lane.
-template <int K>
-__device__ __forceinline__ void bits_find(const int4 *ent4, uint32_t nb, const int32_t (&x)[K], int (&lid)[K]) {
+// Every home bucket is read before any further one; the searches that go on
+// are tracked in one bit mask per lane, and each round issues all of its
+// reads before using any.
+template <uint32_t NB, int K>
+__device__ __forceinline__ void bits_find(const int4 *ent4, const int32_t (&x)[K], int (&lid)[K]) {
   static_assert(K <= 32, "pending searches are one bit each");
   uint32_t b[K];
   int4 e[K];
 #pragma unroll
   for (int k = 0; k < K; k++) {
-    b[k] = bits_bucket(x[k], nb);
+    b[k] = bits_bucket<NB>(x[k]);
     e[k] = ent4[b[k]];
   }
   uint32_t pend = 0;
 #pragma unroll
   for (int k = 0; k < K; k++) {
-    lid[k] = (x[k] >= 0 && e[k].x == x[k]) ? e[k].y : (x[k] >= 0 && e[k].z == x[k]) ? e[k].w : 0;
-    pend |= (uint32_t)(x[k] >= 0 && lid[k] == 0 && e[k].z != kEmpty) << k;
+    lid[k] = (x[k] >= 0 && e[k].x == x[k]) ? (e[k].y & kBitsIdMask)
+           : (x[k] >= 0 && e[k].z == x[k]) ? (e[k].w & kBitsIdMask) : 0;
+    pend |= (uint32_t)(x[k] >= 0 && lid[k] == 0 && (e[k].w & kBitsOverflow) != 0) << k;
   }
   while (pend) {
 #pragma unroll
+    for (int k = 0; k < K; k++) b[k] = ((pend >> k) & 1u) ? (b[k] + 1 == NB ? 0 : b[k] + 1) : b[k];
+#pragma unroll
+    for (int k = 0; k < K; k++)
+      if ((pend >> k) & 1u) e[k] = ent4[b[k]];
+#pragma unroll
     for (int k = 0; k < K; k++) {
       if ((pend >> k) & 1u) {
-        b[k] = b[k] + 1 == nb ? 0 : b[k] + 1;
-        const int4 f = ent4[b[k]];
-        lid[k] = f.x == x[k] ? f.y : f.z == x[k] ? f.w : 0;
-        if (lid[k] != 0 || f.z == kEmpty) pend &= ~(1u << k);
+        lid[k] = e[k].x == x[k] ? (e[k].y & kBitsIdMask) : e[k].z == x[k] ? (e[k].w & kBitsIdMask) : 0;
+        if (lid[k] != 0 || (e[k].w & kBitsOverflow) == 0) pend &= ~(1u << k);
       }
     }
   }
@@ -1655,7 +1674,7 @@ __device__ __forceinline__ void bits_chunk_end(const int64_t *toffs, int j0, int
 template <int NPL, int TC>
 __device__ __forceinline__ void bits_s_pass(const SimArgs &a, BitsLds<TC> &L, int64_t sb, int al, int amax, int q0,
                                             int qs, uint32_t (&lo)[NPL], uint32_t (&hi)[NPL]) {
-  constexpr uint32_t NB = TC;  // buckets of two slots
+  constexpr uint32_t HB = BitsHash<TC>::kNB;  // buckets of two slots
   const int4 *ent4 = reinterpret_cast<const int4 *>(L.h.ent);
   const int lane = threadIdx.x & 63;
   const unsigned long long rowbit = 1ull << lane;
@@ -1689,7 +1708,7 @@ __device__ __forceinline__ void bits_s_pass(const SimArgs &a, BitsLds<TC> &L, in
         x[4 * k + 3] = f ? -1 : rr.w;
       }
       int lid[8];
-      bits_find<8>(ent4, NB, x, lid);
+      bits_find<HB>(ent4, x, lid);
       // only ids of the chunk are marked (most translations miss it; marking
       // the misses in one shared slot would serialise the atomics)
 #pragma unroll
@@ -1706,7 +1725,7 @@ __device__ __forceinline__ void bits_s_pass(const SimArgs &a, BitsLds<TC> &L, in
           for (int e = 0; e < ra[k].z; e++) {
             const int32_t y[1] = {a.lex.vals[ra[k].y + e]};
             int l[1];
-            bits_find<1>(ent4, NB, y, l);
+            bits_find<HB>(ent4, y, l);
             if (l[0]) atomicOr(&B[l[0]], rowbit);
             c[k] |= D[l[0]];
           }
@@ -1815,7 +1834,7 @@ __device__ __forceinline__ void bits_load(const uint64_t *src, uint32_t (&lo)[NP
 template <int TC>
 __global__ __launch_bounds__(kBitsThreads, TC <= 1280 ? 3 : 2) void sim_bits_kernel(SimArgs a) {
   __shared__ BitsLds<TC> L;
-  constexpr uint32_t NS = 2 * TC;
+  constexpr uint32_t NS = 2 * BitsHash<TC>::kNB;  // hash slots
   constexpr int kTpt = (TC + kBitsThreads - 1) / kBitsThreads;  // staged tokens per thread
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -1845,8 +1864,12 @@ __global__ __launch_bounds__(kBitsThreads, TC <= 1280 ? 3 : 2) void sim_bits_ker
         // ---- stage the chunk: ids -> local ids, sentences, D ----
         if (tid < 64) bits_chunk_end<TC>(toffs, j0, m, a.n_tgt_tok, &L.j1, L.ends);
         if (tid == 0) L.nlid = 0;
-        for (int s = tid; s < (int)NS; s += kBitsThreads) L.h.ent[s] = make_int2(kEmpty, 0);
-        for (int s = tid; s < TC + 2; s += kBitsThreads) L.d.db.D[s] = 0, L.d.db.B[s] = 0;
+        {  // 16-byte stores: the hash to {empty, 0}, D and B to 0
+          int4 *e4 = reinterpret_cast<int4 *>(L.h.ent);
+          for (int s = tid; s < (int)NS / 2; s += kBitsThreads) e4[s] = make_int4(kEmpty, 0, kEmpty, 0);
+          uint4 *d4 = reinterpret_cast<uint4 *>(&L.d.db);
+          for (int s = tid; s < TC + 2; s += kBitsThreads) d4[s] = make_uint4(0u, 0u, 0u, 0u);
+        }
         __syncthreads();
         const int j1 = L.j1, nj = j1 - j0;
         const int64_t tbase = clamp64(toffs[j0], 0, a.n_tgt_tok);
@@ -1895,7 +1918,7 @@ __global__ __launch_bounds__(kBitsThreads, TC <= 1280 ? 3 : 2) void sim_bits_ker
             for (int step = kJcap / 2; step >= 1; step >>= 1)
               if (lo + step < nj && L.toff_o[lo + step] <= p) lo += step;
             const int dst = L.toff[lo] + (p - L.toff_o[lo]);
-            if (xs[u] >= 0) h = bits_insert(L.h.ent, (uint32_t)TC, xs[u], fresh);
+            if (xs[u] >= 0) h = bits_insert<BitsHash<TC>::kNB>(L.h.ent, xs[u], fresh);
             L.tdoc[dst] = (uint16_t)h;
             L.tsen[dst] = (uint8_t)lo;
           }
@@ -1905,14 +1928,14 @@ __global__ __launch_bounds__(kBitsThreads, TC <= 1280 ? 3 : 2) void sim_bits_ker
             int base = 0;
             if (lane == lead) base = atomicAdd(&L.nlid, __popcll(nb));
             base = __builtin_amdgcn_readlane(base, lead);
-            if (fresh) L.h.ent[h].y = 1 + base + __popcll(nb & ((1ull << lane) - 1));
+            if (fresh) atomicOr(&L.h.ent[h].y, 1 + base + __popcll(nb & ((1ull << lane) - 1)));  // keeps a mark
           }
         }
         __syncthreads();
         const int npad = L.npad;
         for (int q = tid; q < npad; q += kBitsThreads) {
           const uint16_t s = L.tdoc[q];
-          const int id = s == 0xFFFF ? 0 : L.h.ent[s].y;
+          const int id = s == 0xFFFF ? 0 : (L.h.ent[s].y & kBitsIdMask);
           L.tdoc[q] = (uint16_t)id;
           if (id) atomicOr(reinterpret_cast<unsigned long long *>(&L.d.db.D[id]), 1ull << L.tsen[q]);
         }
