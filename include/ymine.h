@@ -260,8 +260,9 @@ ym_status ym_nw_align(ym_ctx *ctx, const float *S, const int32_t *n, const int32
 /* Parameter sweep for the tuned miner (Section 4: penalty and threshold can
  * be adjusted, and this work adds a tuning algorithm for them; Section 5:
  * the NWT variant).  Scores are computed once per chunk and reused for every
- * gap in gaps[0..n_gaps); each gap reruns only the NW kernel, and every
- * threshold in taus[0..n_taus) is applied while counting.  For the reference
+ * gap in gaps[0..n_gaps): one NW launch per chunk sweeps all of them (its
+ * outputs and scratch are held once per gap), and every threshold in
+ * taus[0..n_taus) is applied while counting.  For the reference
  * pairs given as CSR per document pair (truth_off [n_pairs+1], sentence index
  * pairs truth_src / truth_tgt), n_mined[g * n_taus + t] receives the number
  * of accepted pairs and n_correct[...] how many of them are reference pairs;

@@ -439,15 +439,27 @@ ym_status ym_tune(ym_ctx *c, const ym_lexicon *L, const ym_batch *b, const float
   if (!e) e = hipMemcpyAsync(d_taus, taus, (size_t)n_taus * 4, hipMemcpyHostToDevice, c->stream);
   if (!e) e = hipMemsetAsync(d_mined, 0, 2 * s4, c->stream);
   if (e) return hip_fail(e, "tune upload");
+  // every gap of the sweep in one NW launch per chunk: the NW regions of the
+  // workspace are laid out once per gap, H[n][m] goes to a scratch array
+  CallBuf gbuf;
+  const size_t sg = a256((size_t)n_gaps * 4), sa = a256((size_t)n_gaps * std::max<int64_t>(P, 1) * 4);
+  if ((s = gbuf.reserve(sg + sa))) return s;
+  float *d_gaps = (float *)gbuf.ptr, *d_align = (float *)((char *)gbuf.ptr + sg);
+  if ((e = hipMemcpyAsync(d_gaps, gaps, (size_t)n_gaps * 4, hipMemcpyHostToDevice, c->stream))) return hip_fail(e, "gaps upload");
   std::vector<std::pair<int64_t, int64_t>> chunks;
   const size_t head = trans_bytes(info.n_src_tok);
-  const size_t full = full_workspace(b->src_doc_off, b->tgt_doc_off, P, info.n_src_tok);
-  const size_t wsb = std::max(std::min(full, c->arena_limit + head), min_workspace(b->src_doc_off, b->tgt_doc_off, P, info.n_src_tok));
-  if ((s = plan_chunks(b->src_doc_off, b->tgt_doc_off, P, wsb - head, chunks))) return s;
+  size_t full = 16 * 256 + head, least = 0;
+  for (int64_t p = 0; p < P; p++) {
+    const size_t pb = pair_bytes(b->src_doc_off[p + 1] - b->src_doc_off[p], b->tgt_doc_off[p + 1] - b->tgt_doc_off[p], n_gaps);
+    full += pb;
+    least = std::max(least, pb);
+  }
+  const size_t wsb = std::max(std::min(full, c->arena_limit + head), head + 16 * 256 + least);
+  if ((s = plan_chunks(b->src_doc_off, b->tgt_doc_off, P, wsb - head, chunks, 0, n_gaps))) return s;
   std::vector<Chunk> lay(chunks.size());
   size_t need = 256;
   for (size_t k = 0; k < chunks.size(); k++) {
-    lay[k].layout(b->src_doc_off, b->tgt_doc_off, chunks[k].first, chunks[k].second, c->item_rows);
+    lay[k].layout(b->src_doc_off, b->tgt_doc_off, chunks[k].first, chunks[k].second, c->item_rows, n_gaps);
     need = std::max(need, lay[k].bytes);
   }
   if ((s = c->ws.reserve(head + need))) return s;
@@ -458,17 +470,22 @@ ym_status ym_tune(ym_ctx *c, const ym_lexicon *L, const ym_batch *b, const float
     DebugOut sim;
     sim.sim_only = true;  // scores once per chunk, kept in the workspace
     if ((s = run_chunk(c, L, d, &prm, b->src_doc_off, b->tgt_doc_off, ch, ws, o, c->stream, &sim))) return s;
+    DebugOut nw;
+    nw.reuse_S = true;
+    nw.gaps = d_gaps;
+    nw.align_stride = std::max<int64_t>(P, 1);
+    ym_device_out og = o;
+    og.align_score = d_align;
+    ym_params pg = prm;
+    pg.threshold = -INFINITY;  // keep every diagonal move; thresholds are applied while counting
+    if ((s = run_chunk(c, L, d, &pg, b->src_doc_off, b->tgt_doc_off, ch, ws, og, c->stream, &nw))) return s;
     for (int gi = 0; gi < n_gaps; gi++) {
-      DebugOut nw;
-      nw.reuse_S = true;
-      ym_params pg = prm;
-      pg.gap = gaps[gi];
-      pg.threshold = -INFINITY;  // keep every diagonal move; thresholds are applied while counting
-      if ((s = run_chunk(c, L, d, &pg, b->src_doc_off, b->tgt_doc_off, ch, ws, o, c->stream, &nw))) return s;
-      e = launch_tune_count((const PairDesc *)(ws + ch.off_descs), ch.np, ch.p0, (const int32_t *)(ws + ch.off_counts),
-                            (const int32_t *)(ws + ch.off_ssrc), (const int32_t *)(ws + ch.off_stgt),
-                            (const float *)(ws + ch.off_sscore), d_toff, d_tsrc, d_ttgt, d_taus, n_taus,
-                            d_mined + (size_t)gi * n_taus, d_corr + (size_t)gi * n_taus, c->stream);
+      e = launch_tune_count((const PairDesc *)(ws + ch.off_descs), ch.np, ch.p0,
+                            (const int32_t *)(ws + ch.off_counts) + (size_t)gi * ch.np,
+                            (const int32_t *)(ws + ch.off_ssrc) + (size_t)gi * ch.slots,
+                            (const int32_t *)(ws + ch.off_stgt) + (size_t)gi * ch.slots,
+                            (const float *)(ws + ch.off_sscore) + (size_t)gi * ch.slots, d_toff, d_tsrc, d_ttgt, d_taus,
+                            n_taus, d_mined + (size_t)gi * n_taus, d_corr + (size_t)gi * n_taus, c->stream);
       if (e) return hip_fail(e, "tune count");
     }
   }

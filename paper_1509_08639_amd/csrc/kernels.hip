@@ -1521,6 +1521,9 @@ constexpr int kBitsWide = 11;   // planes for counts <= 2047 (sentences of at mo
 template <int TC>
 struct BitsHash {
   static constexpr uint32_t kNB = TC;
+  // groups of four source positions per iteration of the source pass (the
+  // larger chunk size runs two workgroups per CU, with registers to spare)
+  static constexpr int kGroups = TC >= 2048 ? 2 : 1;
 };
 template <int TC>
 struct BitsLds {
@@ -1667,35 +1670,38 @@ __device__ __forceinline__ void bits_chunk_end(const int64_t *toffs, int j0, int
   ends[lane] = (int)clamp64(e, 0, 1 << 30);
 }
 
-// Source pass over the positions q = q0 + qs (4 u + k) of this lane's row
+// Source pass over the positions q = q0 + qs (4 G u + k) of this lane's row
 // (record base sb, length al; amax: the longest row of the strip): marks B and
 // adds, per position, the set of the chunk's sentences meeting its
-// translations into the planes (lo: sentences 0-31, hi: 32-63).
-template <int NPL, int TC>
+// translations into the planes (lo: sentences 0-31, hi: 32-63).  G groups of
+// four positions per iteration (their lookups overlap); the next iteration's
+// records are fetched while this one is worked on.
+template <int NPL, int TC, int G>
 __device__ __forceinline__ void bits_s_pass(const SimArgs &a, BitsLds<TC> &L, int64_t sb, int al, int amax, int q0,
                                             int qs, uint32_t (&lo)[NPL], uint32_t (&hi)[NPL]) {
   constexpr uint32_t HB = BitsHash<TC>::kNB;  // buckets of two slots
+  constexpr int NR = 4 * G;                   // records per iteration
   const int4 *ent4 = reinterpret_cast<const int4 *>(L.h.ent);
   const int lane = threadIdx.x & 63;
   const unsigned long long rowbit = 1ull << lane;
   unsigned long long *B = reinterpret_cast<unsigned long long *>(L.d.db.B);
   const uint64_t *D = L.d.db.D;
-  auto fetch = [&](int u, int4 (&r)[4]) {
+  auto fetch = [&](int u, int4 (&r)[NR]) {
 #pragma unroll
-    for (int k = 0; k < 4; k++) {
-      const int q = q0 + qs * (4 * u + k);
+    for (int k = 0; k < NR; k++) {
+      const int q = q0 + qs * (NR * u + k);
       r[k] = q < al ? a.trans[sb + q] : make_int4(-1, -1, -1, -1);
     }
   };
-  int4 ra[4];
+  int4 ra[NR];
   fetch(0, ra);
-  for (int u = 0; q0 + qs * 4 * u < amax; u++) {
-    int4 rb[4];
+  for (int u = 0; q0 + qs * NR * u < amax; u++) {
+    int4 rb[NR];
     fetch(u + 1, rb);
     bool far = false;
-    uint64_t c[4];
+    uint64_t c[NR];
 #pragma unroll
-    for (int hf = 0; hf < 2; hf++) {  // two records at a time (register pressure)
+    for (int hf = 0; hf < NR / 2; hf++) {  // two records at a time (register pressure)
       int32_t x[8];
 #pragma unroll
       for (int k = 0; k < 2; k++) {
@@ -1720,7 +1726,7 @@ __device__ __forceinline__ void bits_s_pass(const SimArgs &a, BitsLds<TC> &L, in
     }
     if (far) {
 #pragma unroll
-      for (int k = 0; k < 4; k++) {
+      for (int k = 0; k < NR; k++) {
         if (ra[k].x == -2) {
           for (int e = 0; e < ra[k].z; e++) {
             const int32_t y[1] = {a.lex.vals[ra[k].y + e]};
@@ -1732,16 +1738,17 @@ __device__ __forceinline__ void bits_s_pass(const SimArgs &a, BitsLds<TC> &L, in
         }
       }
     }
-    bits_add4<NPL>(lo, (uint32_t)c[0], (uint32_t)c[1], (uint32_t)c[2], (uint32_t)c[3]);
-    bits_add4<NPL>(hi, (uint32_t)(c[0] >> 32), (uint32_t)(c[1] >> 32), (uint32_t)(c[2] >> 32), (uint32_t)(c[3] >> 32));
 #pragma unroll
-    for (int k = 0; k < 4; k++) ra[k] = rb[k];
+    for (int g = 0; g < G; g++) {
+      bits_add4<NPL>(lo, (uint32_t)c[4 * g], (uint32_t)c[4 * g + 1], (uint32_t)c[4 * g + 2], (uint32_t)c[4 * g + 3]);
+      bits_add4<NPL>(hi, (uint32_t)(c[4 * g] >> 32), (uint32_t)(c[4 * g + 1] >> 32), (uint32_t)(c[4 * g + 2] >> 32),
+                     (uint32_t)(c[4 * g + 3] >> 32));
+    }
+#pragma unroll
+    for (int k = 0; k < NR; k++) ra[k] = rb[k];
   }
 }
 
-// Target pass over blocks of four positions k0, k0 + ks, ... of this lane's
-// sentence j: adds B of each position's id into the planes (lo: rows 0-31,
-// hi: 32-63).
 template <int NPL, int TC>
 __device__ __forceinline__ void bits_t_pass(const BitsLds<TC> &L, int nj, int k0, int ks, uint32_t (&lo)[NPL],
                                             uint32_t (&hi)[NPL]) {
@@ -1948,7 +1955,7 @@ __global__ __launch_bounds__(kBitsThreads, TC <= 1280 ? 3 : 2) void sim_bits_ker
         const bool narrow = amax < 64 && L.bmax < 64;
         if (narrow) {
           uint32_t slo[kBitsNarrow] = {}, shi[kBitsNarrow] = {}, tlo[kBitsNarrow] = {}, thi[kBitsNarrow] = {};
-          bits_s_pass<kBitsNarrow>(a, L, sb, al, amax, wv, kBitsWaves, slo, shi);
+          bits_s_pass<kBitsNarrow, TC, BitsHash<TC>::kGroups>(a, L, sb, al, amax, wv, kBitsWaves, slo, shi);
           __syncthreads();  // B complete; the hash is no longer read
           uint64_t *xs_s = L.h.xch, *xs_t = L.h.xch + (kBitsWaves - 1) * kBitsNarrow * 64;
           if (wv > 0) bits_store<kBitsNarrow>(xs_s + (wv - 1) * kBitsNarrow * 64, slo, shi);
@@ -2024,7 +2031,7 @@ __global__ __launch_bounds__(kBitsThreads, TC <= 1280 ? 3 : 2) void sim_bits_ker
           // sentences of more than 63 tokens: one wave counts, in 11 planes
           if (wv == 0) {
             uint32_t slo[kBitsWide] = {}, shi[kBitsWide] = {}, tlo[kBitsWide] = {}, thi[kBitsWide] = {};
-            bits_s_pass<kBitsWide>(a, L, sb, al, amax, 0, 1, slo, shi);
+            bits_s_pass<kBitsWide, TC, 1>(a, L, sb, al, amax, 0, 1, slo, shi);
             wave_sync();
             bits_t_pass<kBitsWide>(L, nj, 0, 4, tlo, thi);
 #pragma unroll
@@ -2495,10 +2502,28 @@ __device__ __forceinline__ void nw_pair(const NwArgs &a, const PairDesc &d, int6
   nw_finish<kLds>(a, d, p, dirs, hnm);
 }
 
+// The arguments of gap penalty blockIdx.y of a launch that sweeps several.
+__device__ __forceinline__ NwArgs nw_gap_view(const NwArgs &a0) {
+  NwArgs a = a0;
+  if (a.gaps) {
+    const int64_t g = blockIdx.y;
+    a.gap = a.gaps[g];
+    a.dir_scratch += g * a.g_dirs;
+    a.row_scratch += g * a.g_rows;
+    a.slot_src += g * a.g_slots;
+    a.slot_tgt += g * a.g_slots;
+    a.slot_score += g * a.g_slots;
+    a.counts += g * a.g_counts;
+    a.align += g * a.g_align;
+  }
+  return a;
+}
+
 // NPW pairs per workgroup, one wave each (waves never synchronise with each
 // other).  Large pairs (nw_is_big) are left to nw_big_kernel.
 template <int NPW>
-__global__ __launch_bounds__(64 * NPW) void nw_kernel(NwArgs a) {
+__global__ __launch_bounds__(64 * NPW) void nw_kernel(NwArgs a0) {
+  const NwArgs a = nw_gap_view(a0);
   __shared__ uint32_t sdir_all[NPW][kDirLds];
   __shared__ float srow_all[NPW][kRowLds];
   const int wv = NPW == 1 ? 0 : __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -2526,7 +2551,8 @@ __global__ __launch_bounds__(64 * NPW) void nw_kernel(NwArgs a) {
 // kNwWaitTicks), and the pair is then reported with no accepted pairs, a NaN
 // score and the call's status word set, which the host turns into an error.
 // After the sweep, wave 0 traces back.
-__global__ __launch_bounds__(64 * kNwBigWaves) void nw_big_kernel(NwArgs a) {
+__global__ __launch_bounds__(64 * kNwBigWaves) void nw_big_kernel(NwArgs a0) {
+  const NwArgs a = nw_gap_view(a0);
   __shared__ int64_t prog[kNwBigWaves];
   __shared__ int abort_flag;
   __shared__ float s_hnm;
@@ -2760,21 +2786,22 @@ hipError_t launch_similarity(const SimArgs &a, int grid, int variant, hipStream_
 
 hipError_t launch_nw(const NwArgs &a, int pairs_per_group, hipStream_t st) {
   if (a.n_pairs <= 0) return hipSuccess;
+  const unsigned G = a.gaps ? (unsigned)std::max(a.n_gaps, 1) : 1u;  // grid y: gap penalty
   if (a.n_big > 0) {
-    hipLaunchKernelGGL(nw_big_kernel, dim3((unsigned)std::min<int64_t>(a.n_big, 1024)), dim3(64 * kNwBigWaves), 0, st,
-                       a);
+    hipLaunchKernelGGL(nw_big_kernel, dim3((unsigned)std::min<int64_t>(a.n_big, 1024), G), dim3(64 * kNwBigWaves), 0,
+                       st, a);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   switch (pairs_per_group) {
     case 1:
-      hipLaunchKernelGGL(nw_kernel<1>, dim3((unsigned)a.n_pairs), dim3(64), 0, st, a);
+      hipLaunchKernelGGL(nw_kernel<1>, dim3((unsigned)a.n_pairs, G), dim3(64), 0, st, a);
       break;
     case 2:
-      hipLaunchKernelGGL(nw_kernel<2>, dim3((unsigned)((a.n_pairs + 1) / 2)), dim3(128), 0, st, a);
+      hipLaunchKernelGGL(nw_kernel<2>, dim3((unsigned)((a.n_pairs + 1) / 2), G), dim3(128), 0, st, a);
       break;
     case 4:
-      hipLaunchKernelGGL(nw_kernel<4>, dim3((unsigned)((a.n_pairs + 3) / 4)), dim3(256), 0, st, a);
+      hipLaunchKernelGGL(nw_kernel<4>, dim3((unsigned)((a.n_pairs + 3) / 4), G), dim3(256), 0, st, a);
       break;
     default:
       return hipErrorInvalidValue;

@@ -113,21 +113,31 @@ static inline int64_t nw_global_row_floats(int64_t n, int64_t m) {
 }
 static inline bool nw_needs_global_row(int64_t n, int64_t m) { return nw_global_row_floats(n, m) > 0; }
 
-size_t pair_bytes(int64_t n, int64_t m) {
-  size_t b = sizeof(PairDesc) + 4 /*count*/ + 8 /*moves off*/ + 4 /*NW launch order*/;
-  b += (size_t)((n + kMinItemRows - 1) / kMinItemRows) * sizeof(SimItem);  // bound over item sizes
-  b += (size_t)score_block(n, m) * 4;
+// The part of a pair's workspace that the NW kernel writes: its copy is
+// needed once per gap penalty swept in one launch.
+static size_t pair_nw_bytes(int64_t n, int64_t m) {
+  size_t b = 4 /*count*/;
   if (nw_needs_global_dirs(n, m)) b += (size_t)(n * nw_dir_row_words(m)) * 4;
   b += (size_t)nw_global_row_floats(n, m) * 4;
-  if (nw_is_big(n)) b += 4;  // its entry in the list of large pairs
   b += (size_t)std::min(n, m) * 12;
   return b;
 }
 
-static const size_t kChunkSlack = 16 * 256;  // alignment padding of the regions
+size_t pair_bytes(int64_t n, int64_t m, int n_gaps) {
+  size_t b = sizeof(PairDesc) + 8 /*moves off*/ + 4 /*NW launch order*/;
+  b += (size_t)((n + kMinItemRows - 1) / kMinItemRows) * sizeof(SimItem);  // bound over item sizes
+  b += (size_t)score_block(n, m) * 4;
+  if (nw_is_big(n)) b += 4;  // its entry in the list of large pairs
+  b += (size_t)std::max(n_gaps, 1) * pair_nw_bytes(n, m);
+  return b;
+}
 
-ym_status Chunk::layout(const int64_t *sdo, const int64_t *tdo, int64_t p0_, int64_t p1_, int item_rows_) {
+static const size_t kChunkSlack = 16 * 256;  // alignment padding of the regions (fewer than 16 of them)
+
+ym_status Chunk::layout(const int64_t *sdo, const int64_t *tdo, int64_t p0_, int64_t p1_, int item_rows_,
+                        int n_gaps_) {
   item_rows = item_rows_;
+  n_gaps = std::max(n_gaps_, 1);
   p0 = p0_;
   p1 = p1_;
   np = p1 - p0;
@@ -164,18 +174,21 @@ ym_status Chunk::layout(const int64_t *sdo, const int64_t *tdo, int64_t p0_, int
   host_bytes = o;
   off_S = o;
   o = align256(o + (size_t)s_slots * 4);
+  // the regions the NW kernel writes, one copy per gap penalty of the launch
+  // (copy g starts g * its single size further on)
+  const size_t G = (size_t)n_gaps;
   off_dirs = o;
-  o = align256(o + (size_t)dir_words * 4);
+  o = align256(o + G * (size_t)dir_words * 4);
   off_rows = o;
-  o = align256(o + (size_t)row_floats * 4);
+  o = align256(o + G * (size_t)row_floats * 4);
   off_ssrc = o;
-  o = align256(o + (size_t)slots * 4);
+  o = align256(o + G * (size_t)slots * 4);
   off_stgt = o;
-  o = align256(o + (size_t)slots * 4);
+  o = align256(o + G * (size_t)slots * 4);
   off_sscore = o;
-  o = align256(o + (size_t)slots * 4);
+  o = align256(o + G * (size_t)slots * 4);
   off_counts = o;
-  o = align256(o + (size_t)np * 4);
+  o = align256(o + G * (size_t)np * 4);
   bytes = o;
   return YM_OK;
 }
@@ -639,7 +652,7 @@ static const size_t kPlanSlack = 6 * 256;  // alignment padding of the plan's fi
 // Split pairs [0, n_pairs) into chunks whose workspace fits `ws_bytes` and,
 // when `plan_cap` is not 0, whose plan fits `plan_cap` bytes.
 ym_status plan_chunks(const int64_t *sdo, const int64_t *tdo, int64_t n_pairs, size_t ws_bytes,
-                      std::vector<std::pair<int64_t, int64_t>> &chunks, size_t plan_cap) {
+                      std::vector<std::pair<int64_t, int64_t>> &chunks, size_t plan_cap, int n_gaps) {
   chunks.clear();
   int64_t p = 0;
   for (int64_t q = 0; q < n_pairs; q++) {
@@ -651,7 +664,7 @@ ym_status plan_chunks(const int64_t *sdo, const int64_t *tdo, int64_t n_pairs, s
     int64_t q = p;
     while (q < n_pairs) {
       const int64_t n = sdo[q + 1] - sdo[q], m = tdo[q + 1] - tdo[q];
-      const size_t b = pair_bytes(n, m), h = plan_cap ? pair_plan_bytes(n, m) : 0;
+      const size_t b = pair_bytes(n, m, n_gaps), h = plan_cap ? pair_plan_bytes(n, m) : 0;
       if (q > p && (acc + b > ws_bytes || (plan_cap && plan + h > plan_cap))) break;
       acc += b;
       plan += h;
@@ -762,12 +775,22 @@ ym_status run_chunk(ym_ctx *c, const ym_lexicon *L, const DevBatch &b, const ym_
   n.n_moves = dbg ? dbg->n_moves_dev : nullptr;
   n.wait_ticks = c->nw_wait_ticks;
   n.status = out.status;
+  if (dbg && dbg->gaps) {  // every gap of a sweep in this one launch, outputs per gap
+    n.gaps = dbg->gaps;
+    n.n_gaps = ch.n_gaps;
+    n.g_dirs = ch.dir_words;
+    n.g_rows = ch.row_floats;
+    n.g_slots = ch.slots;
+    n.g_counts = ch.np;
+    n.g_align = dbg->align_stride;
+  }
   if (n.moves) n.moves += dbg->moves_base;
   {
     KernelTimer kt(c, 1, st);
     e = launch_nw(n, c->nw_pairs_per_group, st);
   }
   if (e != hipSuccess) return hip_fail(e, "nw kernel");
+  if (dbg && dbg->gaps) return YM_OK;  // a gap sweep counts from the per-pair slots itself
   {
     KernelTimer kt(c, 2, st);
     e = launch_scan(n.counts, ch.np, out.pair_off + ch.p0, ch.p0 == 0, st);

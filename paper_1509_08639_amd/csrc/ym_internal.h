@@ -141,6 +141,12 @@ struct NwArgs {
   int32_t *n_moves;     // optional [n_pairs] (global index)
   uint64_t wait_ticks;  // limit of one bounded wait of the pipelined sweep (0: give up at once)
   int32_t *status;      // optional: set to kStatusWaitGaveUp when a pair's sweep gives up
+  // Several gap penalties in one launch (grid y = gap index g): gaps[g]
+  // replaces `gap`, and the outputs and scratch of gap g lie g strides (in
+  // elements) after those above.  gaps == nullptr: one gap, `gap`.
+  const float *gaps = nullptr;
+  int32_t n_gaps = 1;
+  int64_t g_dirs = 0, g_rows = 0, g_slots = 0, g_counts = 0, g_align = 0;
 };
 
 // Device status word of a call: 0, or the code of the first device failure.

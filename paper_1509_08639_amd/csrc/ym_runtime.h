@@ -47,6 +47,11 @@ struct DebugOut {
   char *moves_dev = nullptr; // device buffer for paths
   int64_t moves_base = 0;    // offset of this chunk's first pair in moves_dev
   int32_t *n_moves_dev = nullptr;
+  // a gap sweep: the NW kernel runs once for the chunk's n_gaps penalties
+  // gaps[0 .. n_gaps) (device), H[n][m] of gap g at align + g * align_stride,
+  // and the call stops after it
+  const float *gaps = nullptr;
+  int64_t align_stride = 0;
 };
 
 // Workspace layout of one chunk of pairs [p0, p1).
@@ -56,13 +61,15 @@ struct Chunk {
   size_t off_descs = 0, off_items = 0, off_S = 0, off_dirs = 0, off_rows = 0, off_ssrc = 0, off_stgt = 0,
          off_sscore = 0, off_counts = 0, off_moves_off = 0, off_big = 0, off_order = 0, bytes = 0, host_bytes = 0;
   int item_rows = kItemRows;  // source sentences per similarity work item
-  ym_status layout(const int64_t *sdo, const int64_t *tdo, int64_t p0, int64_t p1, int item_rows);
+  int n_gaps = 1;             // copies of the NW regions (gap penalties swept by one NW launch)
+  ym_status layout(const int64_t *sdo, const int64_t *tdo, int64_t p0, int64_t p1, int item_rows, int n_gaps = 1);
   void fill_host(const int64_t *sdo, const int64_t *tdo, char *host) const;
 };
 
 ym_status fail(ym_status code, const char *fmt, ...);
 ym_status hip_fail(hipError_t e, const char *what);
-size_t pair_bytes(int64_t n, int64_t m);
+// Workspace bytes of one pair, with the NW outputs and scratch once per gap penalty of a launch.
+size_t pair_bytes(int64_t n, int64_t m, int n_gaps = 1);
 LexDev lex_dev(const ym_lexicon *L);
 ym_status check_params(const ym_params *p);
 ym_status check_doc_off(const int64_t *o, int64_t n_pairs, const char *what);
@@ -73,7 +80,7 @@ ym_status ensure_table(ym_ctx *c, const ym_params *p, hipStream_t st);
 // Resolve the batch's source tokens into `head` (trans_bytes(n_src_tok) bytes) and point b.trans at it.
 ym_status translate_batch(ym_ctx *c, const ym_lexicon *L, DevBatch &b, char *head, hipStream_t st);
 ym_status plan_chunks(const int64_t *sdo, const int64_t *tdo, int64_t n_pairs, size_t ws_bytes,
-                      std::vector<std::pair<int64_t, int64_t>> &chunks, size_t plan_cap = 0);
+                      std::vector<std::pair<int64_t, int64_t>> &chunks, size_t plan_cap = 0, int n_gaps = 1);
 // Pinned staging buffer for plan uploads and the event that marks its last
 // upload as done (the buffer is rewritten only after that event).
 struct Staging {
