@@ -277,8 +277,10 @@ def served(ymine, synth, ctx, seconds, rate, overload_rate, overload_seconds, lo
     return out
 
 
-def batch_leg(torch, ymine, synth, ctx, k, steps, warmup, max_pairs=0):
-    """A batch workload timed the same way as the headline (secondary figures)."""
+def batch_leg(torch, ymine, synth, ctx, k, steps, warmup, max_pairs=0, tune=True):
+    """A batch workload timed the same way as the headline (secondary
+    figures), with its own autotuned launch configuration (on the whole batch
+    when it has at most 20,000 pairs, else on 20,000 spread over it)."""
     cfg = synth.CONFIGS[k]
     lex = synth.make_lexicon(cfg)
     ids = np.arange(min(cfg.n_pairs, max_pairs) if max_pairs else cfg.n_pairs)
@@ -286,13 +288,20 @@ def batch_leg(torch, ymine, synth, ctx, k, steps, warmup, max_pairs=0):
     w = synth.weights(cfg.seed)
     st = workload_stats(corpus, lex)
     L = ctx.lexicon(lex.src_ids, lex.off, lex.tgt_ids)
+    tuning = None
+    if tune:
+        sample = corpus if corpus.n_pairs <= 20000 else corpus.subset(
+            np.linspace(0, corpus.n_pairs - 1, 20000).astype(np.int64))
+        best, best_ms = ymine.autotune(ctx, L, sample, w, np.float32(-0.2), np.float32(0.5), reps=3)
+        tuning = dict(best, sample_pairs=sample.n_pairs, sample_ms=best_ms)
     dm = ymine.DeviceMiner(ctx, L, corpus)
     sec, kern = timed_passes(torch, ctx, dm, w, np.float32(-0.2), np.float32(0.5), steps, warmup)
     roof = roofline(kern, st, cfg.name)
     r = dict(workload=cfg.name, n_pairs=corpus.n_pairs, cells=st["cells"], ms_per_step=sec * 1e3,
-             pairs_per_s=corpus.n_pairs / sec, gcups=st["cells"] / sec / 1e9, kernels=kern, roofline=roof)
+             pairs_per_s=corpus.n_pairs / sec, gcups=st["cells"] / sec / 1e9, kernels=kern, roofline=roof,
+             tuning=tuning)
     log(f"[bench] {cfg.name}: {sec * 1e3:.3f} ms/step, {corpus.n_pairs / sec:.0f} pairs/s, "
-        f"{st['cells'] / sec / 1e9:.1f} GCUPS")
+        f"{st['cells'] / sec / 1e9:.1f} GCUPS; tuning {tuning}")
     del dm
     L.close()
     torch.cuda.empty_cache()
@@ -313,6 +322,9 @@ def main():
     ap.add_argument("--overload-rate", type=float, default=30000.0, help="arrival rate of the overloaded trace")
     ap.add_argument("--overload-seconds", type=float, default=4.0, help="length of the overloaded trace")
     ap.add_argument("--secondary", type=str, default="1,2", help="other batch workloads to time (comma list, '' none)")
+    ap.add_argument("--tuning", type=str, default="",
+                    help="fixed launch configuration 'sim_kernel,item_rows,nw_pairs_per_group,nw_large' "
+                         "for every leg instead of the autotuner's choices (profiling runs)")
     ap.add_argument("--autotune-pairs", type=int, default=20000,
                     help="pairs of the autotuner's sample, spread over the batch (0: default configuration)")
     ap.add_argument("--workspace-gib", type=float, default=64.0, help="workspace cap of the device form (GiB)")
@@ -358,7 +370,12 @@ def main():
     L = ctx.lexicon(lex.src_ids, lex.off, lex.tgt_ids)
     # autotuner (untimed): launch configuration picked on pairs spread over the batch
     tuning = None
-    if args.autotune_pairs > 0:
+    fixed = [int(x) for x in args.tuning.split(",")] if args.tuning else None
+    if fixed:
+        ymine.set_tuning(ctx, *fixed)
+        tuning = dict(ymine.get_tuning(ctx), fixed=True)
+        log(f"[bench] tuning (fixed): {tuning}")
+    elif args.autotune_pairs > 0:
         ids = np.linspace(0, corpus.n_pairs - 1, min(args.autotune_pairs, corpus.n_pairs)).astype(np.int64)
         sample = synth.generate(cfg, lex, pair_ids=ids)
         t = time.time()
@@ -446,7 +463,10 @@ def main():
     for k in [int(x) for x in args.secondary.split(",") if x.strip()]:
         if k != args.workload:
             secondary[synth.CONFIGS[k].name] = batch_leg(torch, ymine, synth, ctx, k, max(3, args.steps // 2),
-                                                         args.warmup)
+                                                         args.warmup, tune=not fixed)
+    if tuning is not None:  # the served legs run with the headline's configuration
+        ymine.set_tuning(ctx, tuning["sim_kernel"], tuning["item_rows"], tuning["nw_pairs_per_group"],
+                         tuning["nw_large"])
 
     serve = None
     if args.serve_seconds > 0:

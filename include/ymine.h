@@ -312,6 +312,10 @@ typedef struct {
                                  1,280 (3) or 2,048 (4) tokens */
   int32_t item_rows;          /* source sentences per similarity work item: 64, 128 (default) or 256 */
   int32_t nw_pairs_per_group; /* document pairs per NW workgroup, one wave each: 1 (default), 2 or 4 */
+  int32_t nw_large;           /* pairs of 449 or more source sentences, swept with their 64-row strips
+                                 pipelined over several waves: 1 (default) the strips of all such pairs
+                                 spread over every CU (a persistent grid taking strips in dependency
+                                 order); 0 one 16-wave workgroup per pair */
 } ym_tuning;
 
 /* Set / read the configuration.  YM_EINVAL for values outside the lists above. */
@@ -320,8 +324,9 @@ ym_status ym_get_tuning(ym_ctx *ctx, ym_tuning *tuning);
 
 /* Autotuner: times the whole path (similarity, NW, compaction) on `sample`
  * with HIP events on the context's stream, `reps` timed passes per candidate
- * after one untimed pass, first over the nine (sim_kernel, item_rows) pairs and
- * then over the NW workgroup sizes with the best of them.  The fastest
+ * after one untimed pass, first over the fifteen (sim_kernel, item_rows) pairs,
+ * then over the NW workgroup sizes with the best of them, then (when the
+ * sample holds a pair of 449 or more source sentences) both nw_large.  The fastest
  * configuration is applied to the context and returned in *best, its mean
  * time per pass in *best_ms (may be NULL).  On error the previous
  * configuration is kept. */

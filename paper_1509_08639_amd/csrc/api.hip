@@ -92,7 +92,7 @@ int64_t capacity_of(const int64_t *sdo, const int64_t *tdo, int64_t n_pairs) {
 }
 
 size_t full_workspace(const int64_t *sdo, const int64_t *tdo, int64_t n_pairs, int64_t n_src_tok) {
-  size_t b = 16 * 256 + trans_bytes(n_src_tok);
+  size_t b = chunk_fixed_bytes() + trans_bytes(n_src_tok);
   for (int64_t p = 0; p < n_pairs; p++) b += pair_bytes(sdo[p + 1] - sdo[p], tdo[p + 1] - tdo[p]);
   return b;
 }
@@ -100,7 +100,7 @@ size_t full_workspace(const int64_t *sdo, const int64_t *tdo, int64_t n_pairs, i
 size_t min_workspace(const int64_t *sdo, const int64_t *tdo, int64_t n_pairs, int64_t n_src_tok) {
   size_t b = 0;
   for (int64_t p = 0; p < n_pairs; p++) b = std::max(b, pair_bytes(sdo[p + 1] - sdo[p], tdo[p + 1] - tdo[p]));
-  return b + 16 * 256 + trans_bytes(n_src_tok);
+  return b + chunk_fixed_bytes() + trans_bytes(n_src_tok);
 }
 
 // Device output buffers of a host-API call, carved from ctx->outb, with the
@@ -448,13 +448,13 @@ ym_status ym_tune(ym_ctx *c, const ym_lexicon *L, const ym_batch *b, const float
   if ((e = hipMemcpyAsync(d_gaps, gaps, (size_t)n_gaps * 4, hipMemcpyHostToDevice, c->stream))) return hip_fail(e, "gaps upload");
   std::vector<std::pair<int64_t, int64_t>> chunks;
   const size_t head = trans_bytes(info.n_src_tok);
-  size_t full = 16 * 256 + head, least = 0;
+  size_t full = chunk_fixed_bytes(n_gaps) + head, least = 0;
   for (int64_t p = 0; p < P; p++) {
     const size_t pb = pair_bytes(b->src_doc_off[p + 1] - b->src_doc_off[p], b->tgt_doc_off[p + 1] - b->tgt_doc_off[p], n_gaps);
     full += pb;
     least = std::max(least, pb);
   }
-  const size_t wsb = std::max(std::min(full, c->arena_limit + head), head + 16 * 256 + least);
+  const size_t wsb = std::max(std::min(full, c->arena_limit + head), head + chunk_fixed_bytes(n_gaps) + least);
   if ((s = plan_chunks(b->src_doc_off, b->tgt_doc_off, P, wsb - head, chunks, 0, n_gaps))) return s;
   std::vector<Chunk> lay(chunks.size());
   size_t need = 256;
@@ -614,6 +614,7 @@ static ym_status check_tuning(const ym_tuning *t) {
     return fail(YM_EINVAL, "item_rows must be 64, 128 or 256");
   if (t->nw_pairs_per_group != 1 && t->nw_pairs_per_group != 2 && t->nw_pairs_per_group != 4)
     return fail(YM_EINVAL, "nw_pairs_per_group must be 1, 2 or 4");
+  if (t->nw_large != 0 && t->nw_large != 1) return fail(YM_EINVAL, "nw_large must be 0 or 1");
   return YM_OK;
 }
 
@@ -621,6 +622,7 @@ static void apply_tuning(ym_ctx *c, const ym_tuning &t) {
   c->sim_variant = t.sim_kernel;
   c->item_rows = t.item_rows;
   c->nw_pairs_per_group = t.nw_pairs_per_group;
+  c->nw_large = t.nw_large;
 }
 
 ym_status ym_set_tuning(ym_ctx *c, const ym_tuning *t) {
@@ -638,6 +640,7 @@ ym_status ym_get_tuning(ym_ctx *c, ym_tuning *t) {
   t->sim_kernel = c->sim_variant;
   t->item_rows = c->item_rows;
   t->nw_pairs_per_group = c->nw_pairs_per_group;
+  t->nw_large = c->nw_large;
   return YM_OK;
 }
 
@@ -679,7 +682,9 @@ ym_status ym_autotune(ym_ctx *c, const ym_lexicon *L, const ym_batch *b, const y
     if (e0) hipEventDestroy(e0);
     return hip_fail(e, "event create");
   }
-  const ym_tuning before{c->sim_variant, c->item_rows, c->nw_pairs_per_group};
+  bool has_big = false;
+  for (int64_t q = 0; q < P && !has_big; q++) has_big = nw_is_big(b->src_doc_off[q + 1] - b->src_doc_off[q]);
+  const ym_tuning before{c->sim_variant, c->item_rows, c->nw_pairs_per_group, c->nw_large};
   auto time_cfg = [&](const ym_tuning &t, double &ms) -> ym_status {
     apply_tuning(c, t);
     std::vector<Chunk> lay(chunks.size());
@@ -703,7 +708,7 @@ ym_status ym_autotune(ym_ctx *c, const ym_lexicon *L, const ym_batch *b, const y
   for (int v : {4, 3, 2, 1, 0}) {
     if (s) break;
     for (int rows : {64, 128, 256}) {
-      const ym_tuning t{v, rows, before.nw_pairs_per_group};
+      const ym_tuning t{v, rows, before.nw_pairs_per_group, before.nw_large};
       double ms = 0;
       if ((s = time_cfg(t, ms))) break;
       if (ms < win_ms) {
@@ -716,10 +721,19 @@ ym_status ym_autotune(ym_ctx *c, const ym_lexicon *L, const ym_batch *b, const y
   for (int ppg : {1, 2, 4}) {
     if (s) break;
     if (ppg == win.nw_pairs_per_group) continue;
-    const ym_tuning t{win.sim_kernel, win.item_rows, ppg};
+    const ym_tuning t{win.sim_kernel, win.item_rows, ppg, win.nw_large};
     double ms = 0;
     if ((s = time_cfg(t, ms))) break;
     if (ms < win_ms) {
+      win_ms = ms;
+      win = t;
+    }
+  }
+  // ... then how the large pairs are swept, when the sample has any
+  if (!s && has_big) {
+    const ym_tuning t{win.sim_kernel, win.item_rows, win.nw_pairs_per_group, 1 - win.nw_large};
+    double ms = 0;
+    if (!(s = time_cfg(t, ms)) && ms < win_ms) {
       win_ms = ms;
       win = t;
     }

@@ -7,7 +7,8 @@
 //                        a, b < 64, from the current classifier weights
 //   translate_kernel     translation record of every source token of a batch
 //   sim_kernel,
-//   sim_tile_kernel      (a) sentence-pair score matrix of each document pair
+//   sim_tile_kernel,
+//   sim_bits_kernel      (a) sentence-pair score matrix of each document pair
 //   nw_kernel,
 //   nw_big_kernel        (b) Needleman-Wunsch forward pass, traceback and
 //                        threshold filter of each document pair
@@ -66,11 +67,18 @@ __device__ __noinline__ float score_direct(float w0, float w1, float w2, float w
   return (float)(1.0 / (1.0 + e));
 }
 
-// table[((a * L + b) * L + ms) * L + mt] = score of (ms, a, mt, b), L = kTabLen
+// Index of the score of (ms, a, mt, b) in the score table:
+// ((ms * L + mt) * L + a) * L + b with L = kTabLen.  The overlap counts are the
+// outer indices, so the cells of the common small counts (most sentence pairs
+// share a few words at most) read a few 16 KB planes that stay in L2.
+__device__ __forceinline__ int tab_index(int a, int b, int ms, int mt) {
+  return (((ms << kLogTabLen) | mt) << (2 * kLogTabLen)) | (a << kLogTabLen) | b;
+}
+
 __global__ __launch_bounds__(256) void score_table_kernel(float w0, float w1, float w2, float w3, float *table) {
   const int idx = blockIdx.x * 256 + threadIdx.x;
   constexpr int M = kTabLen - 1, B = kLogTabLen;
-  const int mt = idx & M, ms = (idx >> B) & M, b = (idx >> (2 * B)) & M, a = (idx >> (3 * B)) & M;
+  const int b = idx & M, a = (idx >> B) & M, mt = (idx >> (2 * B)) & M, ms = (idx >> (3 * B)) & M;
   table[idx] = (ms <= a && mt <= b) ? score_direct(w0, w1, w2, w3, ms, a, mt, b) : 0.0f;
 }
 
@@ -746,7 +754,7 @@ __global__ __launch_bounds__(kSimThreads, 3) void sim_kernel(SimArgs a) {
         // hides it from the wait-count bookkeeping
         const int ca = min(ai, kTabLen - 1), cb = min(bl, kTabLen - 1);
         const int cs = min((int)ms, kTabLen - 1), ct = min((int)mt, kTabLen - 1);
-        float sv = a.table[((ca * kTabLen + cb) * kTabLen + cs) * kTabLen + ct];
+        float sv = a.table[tab_index(ca, cb, cs, ct)];
         off = -1;
         if (!jok) return 0.0f;
         if (ai >= kTabLen || bl >= kTabLen) sv = score_direct(a.w0, a.w1, a.w2, a.w3, (int)ms, ai, (int)mt, bl);
@@ -1318,7 +1326,6 @@ __device__ __forceinline__ void tile_work(const SimArgs &a, const PairDesc &d, c
     // Cells l0 + 8k (k = 0..3) of a 32-row half at once: one shift and mask
     // per plane gathers their bits into four bytes.
     float *strip = a.S + d.s_off + (int64_t)(r0 >> 6) * (m + 63) * 64;
-    const uint32_t bl6 = (uint32_t)t.bl << (2 * kLogTabLen);
     for (int h = 0; h < 2; h++) {
       if (32 * h >= R) break;
       for (int l0 = 0; l0 < 8; l0++) {
@@ -1339,8 +1346,7 @@ __device__ __forceinline__ void tile_work(const SimArgs &a, const PairDesc &d, c
           ok[k] = t.jok && l < R;
           const uint32_t ai = (uint32_t)al_s[min(l, 63)];
           const uint32_t ms = (ms4 >> (8 * k)) & 0xFFu, mt = (mt4 >> (8 * k)) & 0xFFu;
-          const uint32_t idx = ((ai << (3 * kLogTabLen)) | bl6) | (ms << kLogTabLen) | mt;
-          sv[k] = ok[k] ? a.table[idx] : 0.0f;
+          sv[k] = ok[k] ? a.table[tab_index((int)ai, t.bl, (int)ms, (int)mt)] : 0.0f;
           pos[k] = (int64_t)tt * R + l;
           if (ok[k] && a.ms_out) {
             const int64_t cell = d.rm_off + (int64_t)(r0 + l) * m + c;
@@ -1359,7 +1365,7 @@ __device__ __forceinline__ void tile_work(const SimArgs &a, const PairDesc &d, c
       if (t.jok) {
         const int ms = (int)bs_get<NPL>(sl, sh, l), mt = (int)bs_get<NPL>(tl, th, l);
         const float sv = (ai < kTabLen && t.bl < kTabLen)
-                             ? a.table[(((ai << kLogTabLen) | t.bl) << (2 * kLogTabLen)) | (ms << kLogTabLen) | mt]
+                             ? a.table[tab_index(ai, t.bl, ms, mt)]
                              : score_direct(a.w0, a.w1, a.w2, a.w3, ms, ai, mt, t.bl);
         a.S[d.s_off + score_pos(r0 + l, c, n, m)] = sv;
         if (a.ms_out) {
@@ -1993,7 +1999,6 @@ __global__ __launch_bounds__(kBitsThreads, TC <= 1280 ? 3 : 2) void sim_bits_ker
           uint32_t sl[kBitsNarrow], sh[kBitsNarrow], tl[kBitsNarrow], th[kBitsNarrow];
           bits_load<kBitsNarrow>(fin_s, sl, sh);
           bits_load<kBitsNarrow>(fin_t, tl, th);
-          const int tb = bj << (2 * kLogTabLen);
           float sv[16];
 #pragma unroll
           for (int g = 0; g < 4; g++) {
@@ -2010,8 +2015,7 @@ __global__ __launch_bounds__(kBitsThreads, TC <= 1280 ? 3 : 2) void sim_bits_ker
               const bool ok = jok && r < R;
               const int ar = __builtin_amdgcn_readlane(al, r);  // wave-uniform row
               const uint32_t ms = (ms4 >> (8 * k)) & 0xFFu, mt = (mt4 >> (8 * k)) & 0xFFu;
-              const int idx = (ar << (3 * kLogTabLen)) | tb | (int)(ms << kLogTabLen) | (int)mt;
-              sv[4 * g + k] = ok ? a.table[idx] : 0.0f;
+              sv[4 * g + k] = ok ? a.table[tab_index(ar, bj, (int)ms, (int)mt)] : 0.0f;
               if (ok && a.ms_out) {
                 const int64_t cell = it.rm_off + (int64_t)(r0 + r) * m + c;
                 a.ms_out[cell] = (int32_t)ms;
@@ -2054,7 +2058,7 @@ __global__ __launch_bounds__(kBitsThreads, TC <= 1280 ? 3 : 2) void sim_bits_ker
             const int ar = __builtin_amdgcn_readlane(al, r);
             if (jok) {
               const float sv = (ar < kTabLen && bj < kTabLen)
-                                   ? a.table[(ar << (3 * kLogTabLen)) | (bj << (2 * kLogTabLen)) | (int)(ms << kLogTabLen) | (int)mt]
+                                   ? a.table[tab_index(ar, bj, (int)ms, (int)mt)]
                                    : score_direct(a.w0, a.w1, a.w2, a.w3, (int)ms, ar, (int)mt, bj);
               strip[(r + c) * R + r] = sv;
               if (a.ms_out) {
@@ -2120,6 +2124,10 @@ struct NwPipe {
   int W = 1;
   int *abort = nullptr;  // LDS flag: a wait ran past its time limit
   uint64_t limit = kNwWaitTicks;  // ticks of the 100 MHz constant counter; 0: give up at once
+  // persistent-grid sweep (tagged boundary rows): this launch's tag and the
+  // pair's give-up flag in global memory
+  uint32_t tag = 0;
+  int32_t *gabort = nullptr;
 };
 
 // Wait until strip `strip` has published at least `cols` columns (or has been
@@ -2147,6 +2155,41 @@ __device__ __forceinline__ bool nw_wait(const NwPipe &pp, int strip, int cols) {
   }
 }
 
+// Entry t of the previous strip's bottom row in the persistent-grid sweep,
+// for the lanes with `need`.  Entries are 8 bytes, {H, tag}, stored with one
+// atomic store by the wave of that strip (possibly on another CU or XCD): an
+// entry carrying this launch's tag holds this launch's value, so no flag or
+// fence is needed.  The wave waits until every needed entry has the tag, for
+// at most the time limit; a give-up (or an earlier one for the same pair)
+// sets the pair's flag, and the sweep goes on with whatever the entries hold.
+__device__ __forceinline__ float nw_row_take(const NwPipe &pp, const uint64_t *row, int t, bool need) {
+  if (pp.limit == 0) {  // failure injection: every wait gives up
+    if ((threadIdx.x & 63) == 0) __hip_atomic_store(pp.gabort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return 0.0f;
+  }
+  uint64_t v = need ? __hip_atomic_load(row + t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0ull;
+  bool ok = !need || (uint32_t)(v >> 32) == pp.tag;
+  if (__builtin_expect(__ballot(!ok) != 0ull, 0)) {
+    const uint64_t t0 = wall_clock64();
+    for (;;) {
+      const int given_up =
+          __builtin_amdgcn_readfirstlane(__hip_atomic_load(pp.gabort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+      if (given_up) break;
+      if (wall_clock64() - t0 > pp.limit) {
+        if ((threadIdx.x & 63) == 0) __hip_atomic_store(pp.gabort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+      if (!ok) {
+        v = __hip_atomic_load(row + t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = (uint32_t)(v >> 32) == pp.tag;
+      }
+      if (__ballot(!ok) == 0ull) break;
+    }
+  }
+  return __uint_as_float((uint32_t)v);
+}
+
 // Publish `cols` columns of strip `strip`'s bottom row (after this wave's row stores).
 __device__ __forceinline__ void nw_publish(const NwPipe &pp, int strip, int cols) {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -2162,12 +2205,17 @@ __device__ __forceinline__ void nw_publish(const NwPipe &pp, int strip, int cols
 // of lanes outside a diagonal are never used.  For strips after the first,
 // lane k also fetches the previous strip's bottom-row value H[64s][t] of the
 // block's step k (handed to lane 0 by readlane).
+template <bool kTagged>
 __device__ __forceinline__ void nw_prefetch(float (&buf)[kNwUnroll], float &rbv, __amdgpu_buffer_rsrc_t rs,
                                             const float *rowbuf, bool use_row, int &d, int lane, int R, int m,
                                             const NwPipe &pp, int s) {
   const int t = d + 1 + lane;
-  if (pp.prog && use_row) nw_wait(pp, s - 1, min(m, d + kNwUnroll) + 1);
-  rbv = (use_row && lane < kNwUnroll && t <= m) ? rowbuf[t] : 0.0f;
+  if (kTagged) {
+    rbv = use_row ? nw_row_take(pp, (const uint64_t *)rowbuf, t, lane < kNwUnroll && t <= m) : 0.0f;
+  } else {
+    if (pp.prog && use_row) nw_wait(pp, s - 1, min(m, d + kNwUnroll) + 1);
+    rbv = (use_row && lane < kNwUnroll && t <= m) ? rowbuf[t] : 0.0f;
+  }
 #pragma unroll
   for (int k = 0; k < kNwUnroll; k++) {
     buf[k] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (d * R + lane) * 4, 0, 0));
@@ -2183,7 +2231,7 @@ __device__ __forceinline__ void nw_prefetch(float (&buf)[kNwUnroll], float &rbv,
 // step: bits 2k..2k+1 of a lane's word hold the code of its cell at step
 // t0 + k, and every lane stores its word once per block.  The last row's H
 // values are kept in registers and handed to the next strip at the block end.
-template <bool kTail, bool kTop>
+template <bool kTail, bool kTop, bool kTagged>
 __device__ __forceinline__ void nw_steps(const float (&buf)[kNwUnroll], float rbv, int t0, int tend, NwLane &L,
                                          int lane, int i, bool rowok, int lastlane, bool keep_row, int m, int Wr,
                                          float g, uint32_t *dirs, float *rowbuf, const NwPipe &pp, int s) {
@@ -2223,7 +2271,16 @@ __device__ __forceinline__ void nw_steps(const float (&buf)[kNwUnroll], float rb
   }
   // this block's words: lane l's cells j = t - l in [1, m]
   const int tl = kTail ? min(t0 + kNwUnroll - 1, tend) : t0 + kNwUnroll - 1;
-  if (rowok && tl >= lane + 1 && t0 <= lane + m) dirs[(int64_t)(i - 1) * Wr + ((t0 >> 4) - (lane >> 4))] = dw;
+  if (rowok && tl >= lane + 1 && t0 <= lane + m) {
+    const int64_t w = (int64_t)(i - 1) * Wr + ((t0 >> 4) - (lane >> 4));
+    // the persistent-grid sweep's words are traced back by a wave that may
+    // run on another CU: 8-byte {word, tag} entries, like its boundary rows
+    if (kTagged)
+      __hip_atomic_store((uint64_t *)dirs + w, ((uint64_t)pp.tag << 32) | dw, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    else
+      dirs[w] = dw;
+  }
   if (keep_row) {
     // lane k stores the last row's H at column t0 + k - lastlane
     float v = 0.0f;
@@ -2233,8 +2290,14 @@ __device__ __forceinline__ void nw_steps(const float (&buf)[kNwUnroll], float rb
       v = lane == k ? x : v;
     }
     const int j = t0 + lane - lastlane;
-    if (lane < kNwUnroll && j >= 0 && j <= m && t0 + lane <= tl) rowbuf[j] = v;
-    if (pp.prog) {
+    if (lane < kNwUnroll && j >= 0 && j <= m && t0 + lane <= tl) {
+      if (kTagged)
+        __hip_atomic_store((uint64_t *)rowbuf + j, ((uint64_t)pp.tag << 32) | __float_as_uint(v), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+      else
+        rowbuf[j] = v;
+    }
+    if (!kTagged && pp.prog) {
       const int cols = min(m, tl - lastlane) + 1;
       if (cols > 0) nw_publish(pp, s, cols);
     }
@@ -2244,7 +2307,9 @@ __device__ __forceinline__ void nw_steps(const float (&buf)[kNwUnroll], float rb
 // One 64-row strip of a pair's sweep.  rowin: the previous strip's bottom
 // row (strips after the first), rowout: this strip's bottom row (strips before
 // the last; may be the same array as rowin for a one-wave sweep, whose reads
-// run ahead of its writes).  Returns H of the strip's last row at column m.
+// run ahead of its writes); kTagged: rows of 8-byte {H, tag} entries (the
+// persistent-grid sweep).  Returns H of the strip's last row at column m.
+template <bool kTagged>
 __device__ __forceinline__ float nw_strip(const NwArgs &a, const PairDesc &d, int s, uint32_t *dirs,
                                           const float *rowin, float *rowout, const NwPipe &pp) {
   const int lane = threadIdx.x & 63;
@@ -2265,30 +2330,30 @@ __device__ __forceinline__ float nw_strip(const NwArgs &a, const PairDesc &d, in
   float bufA[kNwUnroll], bufB[kNwUnroll], rbA, rbB;
   int cd = -1;  // prefetch cursor: step t reads diagonal t-1
   const bool use_row = s > 0;
-  nw_prefetch(bufA, rbA, rs, rowin, use_row, cd, lane, R, m, pp, s);
+  nw_prefetch<kTagged>(bufA, rbA, rs, rowin, use_row, cd, lane, R, m, pp, s);
   int t0 = 0;
   // full blocks of 2 x 16 steps
   for (; t0 + 2 * kNwUnroll - 1 <= tend; t0 += 2 * kNwUnroll) {
-    nw_prefetch(bufB, rbB, rs, rowin, use_row, cd, lane, R, m, pp, s);
+    nw_prefetch<kTagged>(bufB, rbB, rs, rowin, use_row, cd, lane, R, m, pp, s);
     if (s == 0)
-      nw_steps<false, true>(bufA, rbA, t0, tend, L, lane, i, rowok, lastlane, keep_row, m, Wr, g, dirs, rowout, pp, s);
+      nw_steps<false, true, kTagged>(bufA, rbA, t0, tend, L, lane, i, rowok, lastlane, keep_row, m, Wr, g, dirs, rowout, pp, s);
     else
-      nw_steps<false, false>(bufA, rbA, t0, tend, L, lane, i, rowok, lastlane, keep_row, m, Wr, g, dirs, rowout, pp, s);
-    nw_prefetch(bufA, rbA, rs, rowin, use_row, cd, lane, R, m, pp, s);
+      nw_steps<false, false, kTagged>(bufA, rbA, t0, tend, L, lane, i, rowok, lastlane, keep_row, m, Wr, g, dirs, rowout, pp, s);
+    nw_prefetch<kTagged>(bufA, rbA, rs, rowin, use_row, cd, lane, R, m, pp, s);
     if (s == 0)
-      nw_steps<false, true>(bufB, rbB, t0 + kNwUnroll, tend, L, lane, i, rowok, lastlane, keep_row, m, Wr, g, dirs,
+      nw_steps<false, true, kTagged>(bufB, rbB, t0 + kNwUnroll, tend, L, lane, i, rowok, lastlane, keep_row, m, Wr, g, dirs,
                             rowout, pp, s);
     else
-      nw_steps<false, false>(bufB, rbB, t0 + kNwUnroll, tend, L, lane, i, rowok, lastlane, keep_row, m, Wr, g, dirs,
+      nw_steps<false, false, kTagged>(bufB, rbB, t0 + kNwUnroll, tend, L, lane, i, rowok, lastlane, keep_row, m, Wr, g, dirs,
                              rowout, pp, s);
   }
   // the rest: at most two blocks, the last one partial
   for (; t0 <= tend; t0 += kNwUnroll) {
     if (s == 0)
-      nw_steps<true, true>(bufA, rbA, t0, tend, L, lane, i, rowok, lastlane, keep_row, m, Wr, g, dirs, rowout, pp, s);
+      nw_steps<true, true, kTagged>(bufA, rbA, t0, tend, L, lane, i, rowok, lastlane, keep_row, m, Wr, g, dirs, rowout, pp, s);
     else
-      nw_steps<true, false>(bufA, rbA, t0, tend, L, lane, i, rowok, lastlane, keep_row, m, Wr, g, dirs, rowout, pp, s);
-    if (t0 + kNwUnroll <= tend) nw_prefetch(bufA, rbA, rs, rowin, use_row, cd, lane, R, m, pp, s);
+      nw_steps<true, false, kTagged>(bufA, rbA, t0, tend, L, lane, i, rowok, lastlane, keep_row, m, Wr, g, dirs, rowout, pp, s);
+    if (t0 + kNwUnroll <= tend) nw_prefetch<kTagged>(bufA, rbA, rs, rowin, use_row, cd, lane, R, m, pp, s);
   }
   return __shfl(L.h, lastlane);
 }
@@ -2300,11 +2365,29 @@ __device__ __forceinline__ float nw_boundary_only(int n, int m, float g) {
   return h;
 }
 
+// Direction word widx of a pair swept by the persistent grid: its 8-byte
+// {word, tag} entry, read again (bounded) until it carries this launch's tag;
+// a give-up sets the pair's flag (per lane: callable from divergent code).
+__device__ __forceinline__ uint32_t nw_tagged_word(const uint32_t *dirs, int64_t widx, const NwPipe &tp) {
+  const uint64_t *e = (const uint64_t *)dirs + widx;
+  uint64_t v = __hip_atomic_load(e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if ((uint32_t)(v >> 32) != tp.tag) {
+    const uint64_t t0 = wall_clock64();
+    while ((uint32_t)(v >> 32) != tp.tag && wall_clock64() - t0 <= tp.limit) {
+      __builtin_amdgcn_s_sleep(1);
+      v = __hip_atomic_load(e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if ((uint32_t)(v >> 32) != tp.tag) __hip_atomic_store(tp.gabort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  return (uint32_t)v;
+}
+
 // Traceback, threshold filter and outputs of one pair (one wave), once the
-// sweep has written all direction words.
-template <bool kLds>
+// sweep has written all direction words (kTagged: 8-byte entries of the
+// persistent-grid sweep, checked against tp.tag).
+template <bool kLds, bool kTagged = false>
 __device__ __forceinline__ void nw_finish(const NwArgs &a, const PairDesc &d, int64_t p, const uint32_t *dirs,
-                                          float hnm) {
+                                          float hnm, const NwPipe &tp = NwPipe{}) {
   const int lane = threadIdx.x & 63;
   const int n = d.n, m = d.m;
   const int Wr = nw_dir_row_words(m);
@@ -2325,7 +2408,7 @@ __device__ __forceinline__ void nw_finish(const NwArgs &a, const PairDesc &d, in
         const int l = (i - 1) & 63, st = j + l;  // the cell's lane and sweep step
         const int64_t widx = (int64_t)(i - 1) * Wr + ((st >> 4) - (l >> 4));
         if (widx != cur) {
-          word = dirs[widx];
+          word = kLds ? dirs[widx] : kTagged ? nw_tagged_word(dirs, widx, tp) : ((const volatile uint32_t *)dirs)[widx];
           cur = widx;
         }
         const uint32_t code = (word >> (2 * (st & 15))) & 3u;
@@ -2390,6 +2473,25 @@ __device__ __forceinline__ void nw_finish(const NwArgs &a, const PairDesc &d, in
           w0 = row[wlo];
           if (wlo + 1 < Wr) w1 = row[wlo + 1];
           if (wlo + 2 < Wr) w2 = row[wlo + 2];
+        } else if (kTagged) {
+          // only the words the sweep wrote (this row's cells lie in words
+          // lo_w .. hi_w): the others are never read by the walk, and their
+          // entries carry no tag of this launch
+          // (the three loads are issued together; a word without this
+          // launch's tag yet is read again on its own)
+          const uint64_t *e = (const uint64_t *)dirs + (int64_t)r * Wr;
+          const int lo_w = ((l + 1) >> 4) - (l >> 4), hi_w = ((l + m) >> 4) - (l >> 4);
+          const bool k0 = wlo >= lo_w && wlo <= hi_w, k1 = wlo + 1 >= lo_w && wlo + 1 <= hi_w,
+                     k2 = wlo + 2 >= lo_w && wlo + 2 <= hi_w;
+          const uint64_t v0 = k0 ? __hip_atomic_load(e + wlo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0ull;
+          const uint64_t v1 = k1 ? __hip_atomic_load(e + wlo + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0ull;
+          const uint64_t v2 = k2 ? __hip_atomic_load(e + wlo + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0ull;
+          w0 = (uint32_t)v0;
+          w1 = (uint32_t)v1;
+          w2 = (uint32_t)v2;
+          if (k0 && (uint32_t)(v0 >> 32) != tp.tag) w0 = nw_tagged_word(dirs, (int64_t)r * Wr + wlo, tp);
+          if (k1 && (uint32_t)(v1 >> 32) != tp.tag) w1 = nw_tagged_word(dirs, (int64_t)r * Wr + wlo + 1, tp);
+          if (k2 && (uint32_t)(v2 >> 32) != tp.tag) w2 = nw_tagged_word(dirs, (int64_t)r * Wr + wlo + 2, tp);
         } else {
           const volatile uint32_t *vrow = row;
           w0 = vrow[wlo];
@@ -2493,7 +2595,7 @@ __device__ __forceinline__ void nw_pair(const NwArgs &a, const PairDesc &d, int6
   if (d.n > 0 && d.m > 0) {
     const int nstrips = (d.n + 63) >> 6;
     for (int s = 0; s < nstrips; s++) {
-      hnm = nw_strip(a, d, s, dirs, rowbuf, rowbuf, NwPipe{});
+      hnm = nw_strip<false>(a, d, s, dirs, rowbuf, rowbuf, NwPipe{});
       wave_sync_mem();
     }
   } else {
@@ -2515,8 +2617,18 @@ __device__ __forceinline__ NwArgs nw_gap_view(const NwArgs &a0) {
     a.slot_score += g * a.g_slots;
     a.counts += g * a.g_counts;
     a.align += g * a.g_align;
+    a.ctrl += g * a.g_ctrl;
   }
   return a;
+}
+
+// A large pair whose sweep gave up: no accepted pairs, a NaN score, the
+// call's status word set (lane 0).
+__device__ __forceinline__ void nw_report_failed(const NwArgs &a, int64_t p) {
+  a.counts[p] = 0;
+  a.align[a.pair_base + p] = __int_as_float(0x7fc00000);
+  if (a.n_moves) a.n_moves[a.pair_base + p] = 0;
+  if (a.status) __hip_atomic_store(a.status, kStatusWaitGaveUp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // NPW pairs per workgroup, one wave each (waves never synchronise with each
@@ -2574,7 +2686,7 @@ __global__ __launch_bounds__(64 * kNwBigWaves) void nw_big_kernel(NwArgs a0) {
       if (threadIdx.x == 0) s_hnm = nw_boundary_only(d.n, d.m, a.gap);
     } else
     for (int s = wv; s < nstrips; s += kNwBigWaves) {
-      const float h = nw_strip(a, d, s, dirs, s > 0 ? rows + (int64_t)(s - 1) * (d.m + 1) : nullptr,
+      const float h = nw_strip<false>(a, d, s, dirs, s > 0 ? rows + (int64_t)(s - 1) * (d.m + 1) : nullptr,
                                s + 1 < nstrips ? rows + (int64_t)s * (d.m + 1) : nullptr, pp);
       if (s == nstrips - 1 && lane == 0) s_hnm = h;
     }
@@ -2583,18 +2695,92 @@ __global__ __launch_bounds__(64 * kNwBigWaves) void nw_big_kernel(NwArgs a0) {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     if (wv == 0) {
       if (abort_flag) {  // the pair is reported as failed: NaN score, no pairs, status word set
-        if (lane == 0) {
-          a.counts[p] = 0;
-          a.align[a.pair_base + p] = __int_as_float(0x7fc00000);
-          if (a.n_moves) a.n_moves[a.pair_base + p] = 0;
-          if (a.status) __hip_atomic_store(a.status, kStatusWaitGaveUp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
+        if (lane == 0) nw_report_failed(a, p);
       } else {
         nw_finish<false>(a, d, p, dirs, s_hnm);
       }
     }
     __syncthreads();
   }
+}
+
+// Large pairs with their strips spread over the whole GPU.  Every wave of a
+// persistent grid takes tickets from a counter; the tickets are the strips of
+// the large pairs, pair after pair (largest first) and in strip order inside
+// a pair, so strip s - 1 was taken before strip s by a wave that is running
+// or done, and a wait of strip s on it always ends (each wait is also
+// bounded).  Everything one wave hands to another goes through global memory
+// as 8-byte atomic entries {value, tag} that the reader reads again until
+// they carry this launch's tag: the boundary rows (nw_row_take), the
+// direction words and H[n][m].  No cache-wide fence is needed.  A wave that
+// ends a strip counts it in its pair's control word; the wave that counts the
+// last strip traces the pair back (or reports it failed).
+__global__ __launch_bounds__(64 * kNwSplitWaves) void nw_split_kernel(NwArgs a0) {
+  const NwArgs a = nw_gap_view(a0);
+  const int lane = threadIdx.x & 63;
+  int32_t *ctrl = a.ctrl;
+  const uint32_t tag = (uint32_t)ctrl[1];
+  for (;;) {
+    int tk = 0;
+    if (lane == 0) tk = __hip_atomic_fetch_add(ctrl, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    tk = __builtin_amdgcn_readfirstlane(tk);
+    if (tk >= a.n_big_strips) break;
+    const int bi = a.ticket_big[tk];
+    const int s = tk - a.big_strip0[bi];
+    const int64_t p = a.big[bi];
+    const PairDesc d = a.descs[p];
+    // {strips done, give-up flag, {H[n][m], tag} as one 8-byte entry}
+    int32_t *pc = ctrl + kNwCtrlHead + (int64_t)kNwCtrlPerPair * bi;
+    uint64_t *hslot = (uint64_t *)(pc + 2);
+    const int nstrips = (d.n + 63) >> 6;
+    uint32_t *dirs = a.dir_scratch + d.dir_off;
+    float *rows = a.row_scratch + d.row_off;  // bottom row of strip s: 8-byte entries from rows + 2 s (m + 1)
+    NwPipe pp;
+    pp.limit = a.wait_ticks;
+    pp.tag = tag;
+    pp.gabort = pc + 1;
+    float h = 0.0f;
+    if (d.m > 0) {
+      const int64_t rw = 2 * (int64_t)(d.m + 1);
+      h = nw_strip<true>(a, d, s, dirs, s > 0 ? rows + (s - 1) * rw : nullptr, s + 1 < nstrips ? rows + s * rw : nullptr,
+                         pp);
+    } else {  // no target sentence: the boundary alone
+      h = nw_boundary_only(d.n, d.m, a.gap);
+    }
+    if (s == nstrips - 1 && lane == 0)
+      __hip_atomic_store(hslot, ((uint64_t)tag << 32) | __float_as_uint(h), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int done = 0;
+    if (lane == 0) done = __hip_atomic_fetch_add(pc, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    done = __builtin_amdgcn_readfirstlane(done);
+    if (done != nstrips - 1) continue;
+    // the last strip of the pair: H[n][m] once its entry carries the tag, then the traceback
+    float hnm = 0.0f;
+    if (lane == 0) hnm = __uint_as_float(nw_tagged_word((const uint32_t *)hslot, 0, pp));
+    hnm = __shfl(hnm, 0);
+    if (__builtin_amdgcn_readfirstlane(__hip_atomic_load(pc + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == 0)
+      nw_finish<false, true>(a, d, p, dirs, hnm, pp);
+    // a give-up of any wait of the pair, the traceback's included: reported failed
+    if (__builtin_amdgcn_readfirstlane(__hip_atomic_load(pc + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) &&
+        lane == 0)
+      nw_report_failed(a, p);
+  }
+}
+
+// Tags of the persistent-grid NW launches on this device: each launch takes
+// the next (never 0, so memory that was never written carries no valid tag).
+__device__ uint32_t g_nw_tag;
+
+// Control words of a persistent-grid NW launch (one workgroup): counters
+// zeroed and the launch's new tag in every gap penalty's copy.
+__global__ __launch_bounds__(256) void nw_split_begin_kernel(int32_t *ctrl, int64_t per_gap, int n_gaps) {
+  __shared__ uint32_t tag;
+  if (threadIdx.x == 0) {
+    uint32_t t = atomicAdd(&g_nw_tag, 1u) + 1u;
+    if (t == 0) t = atomicAdd(&g_nw_tag, 1u) + 1u;
+    tag = t;
+  }
+  __syncthreads();
+  for (int64_t k = threadIdx.x; k < per_gap * n_gaps; k += 256) ctrl[k] = (k % per_gap) == 1 ? (int32_t)tag : 0;
 }
 
 // ----------------------------------------------------------- compaction
@@ -2787,7 +2973,19 @@ hipError_t launch_similarity(const SimArgs &a, int grid, int variant, hipStream_
 hipError_t launch_nw(const NwArgs &a, int pairs_per_group, hipStream_t st) {
   if (a.n_pairs <= 0) return hipSuccess;
   const unsigned G = a.gaps ? (unsigned)std::max(a.n_gaps, 1) : 1u;  // grid y: gap penalty
-  if (a.n_big > 0) {
+  if (a.n_big > 0 && a.split) {
+    if (!a.ctrl || !a.big_strip0 || !a.ticket_big || a.n_big_strips <= 0) return hipErrorInvalidValue;
+    const int64_t per_gap = kNwCtrlHead + (int64_t)kNwCtrlPerPair * a.n_big;
+    if (G > 1 && a.g_ctrl != per_gap) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(nw_split_begin_kernel, dim3(1), dim3(256), 0, st, a.ctrl, per_gap, (int)G);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t groups = std::min<int64_t>((a.n_big_strips + kNwSplitWaves - 1) / kNwSplitWaves,
+                                             (int64_t)kNwSplitGroupsPerCu * kNwSplitCus);
+    hipLaunchKernelGGL(nw_split_kernel, dim3((unsigned)groups, G), dim3(64 * kNwSplitWaves), 0, st, a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  } else if (a.n_big > 0) {
     hipLaunchKernelGGL(nw_big_kernel, dim3((unsigned)std::min<int64_t>(a.n_big, 1024), G), dim3(64 * kNwBigWaves), 0,
                        st, a);
     const hipError_t e = hipGetLastError();

@@ -104,22 +104,36 @@ void HostBuf::release() {
 static inline bool nw_needs_global_dirs(int64_t n, int64_t m) {
   return nw_is_big(n) || n * nw_dir_row_words(m) > kDirLds;
 }
-// boundary-row floats in global scratch: one row per strip boundary for the
-// pipelined sweep of a large pair, one reused row for a one-wave sweep whose
-// row does not fit LDS
-static inline int64_t nw_global_row_floats(int64_t n, int64_t m) {
-  if (nw_is_big(n)) return ((n + 63) / 64 - 1) * (m + 1);
-  return (n > 64 && m + 1 > kRowLds) ? m + 1 : 0;
+// 4-byte words of a pair's direction codes in global scratch: a large pair
+// gets 8-byte entries (the persistent-grid sweep tags every word; the
+// one-workgroup sweep uses the first half), and every count is even, so every
+// pair's words start 8-byte aligned.
+static inline int64_t nw_global_dir_words(int64_t n, int64_t m) {
+  if (!nw_needs_global_dirs(n, m)) return 0;
+  const int64_t w = n * nw_dir_row_words(m);
+  return nw_is_big(n) ? 2 * w : (w + 1) & ~int64_t(1);
 }
+// boundary-row floats in global scratch: one row per strip boundary for the
+// pipelined sweep of a large pair (8-byte {H, tag} entries, which the
+// persistent-grid sweep needs; the one-workgroup sweep uses the first half),
+// one reused row for a one-wave sweep whose row does not fit LDS.  Always
+// even, so every pair's rows start 8-byte aligned.
+static inline int64_t nw_global_row_floats(int64_t n, int64_t m) {
+  if (nw_is_big(n)) return 2 * ((n + 63) / 64 - 1) * (m + 1);
+  return (n > 64 && m + 1 > kRowLds) ? ((m + 2) & ~int64_t(1)) : 0;
+}
+// tickets of a large pair in the persistent-grid sweep (one per strip)
+static inline int64_t nw_tickets(int64_t n) { return nw_is_big(n) ? (n + 63) / 64 : 0; }
 static inline bool nw_needs_global_row(int64_t n, int64_t m) { return nw_global_row_floats(n, m) > 0; }
 
 // The part of a pair's workspace that the NW kernel writes: its copy is
 // needed once per gap penalty swept in one launch.
 static size_t pair_nw_bytes(int64_t n, int64_t m) {
   size_t b = 4 /*count*/;
-  if (nw_needs_global_dirs(n, m)) b += (size_t)(n * nw_dir_row_words(m)) * 4;
+  b += (size_t)nw_global_dir_words(n, m) * 4;
   b += (size_t)nw_global_row_floats(n, m) * 4;
   b += (size_t)std::min(n, m) * 12;
+  if (nw_is_big(n)) b += 4 * kNwCtrlPerPair;  // its control words
   return b;
 }
 
@@ -127,12 +141,11 @@ size_t pair_bytes(int64_t n, int64_t m, int n_gaps) {
   size_t b = sizeof(PairDesc) + 8 /*moves off*/ + 4 /*NW launch order*/;
   b += (size_t)((n + kMinItemRows - 1) / kMinItemRows) * sizeof(SimItem);  // bound over item sizes
   b += (size_t)score_block(n, m) * 4;
-  if (nw_is_big(n)) b += 4;  // its entry in the list of large pairs
+  if (nw_is_big(n)) b += 8 + 4 * nw_tickets(n);  // its entries in the large-pair list, first tickets, ticket map
   b += (size_t)std::max(n_gaps, 1) * pair_nw_bytes(n, m);
   return b;
 }
 
-static const size_t kChunkSlack = 16 * 256;  // alignment padding of the regions (fewer than 16 of them)
 
 ym_status Chunk::layout(const int64_t *sdo, const int64_t *tdo, int64_t p0_, int64_t p1_, int item_rows_,
                         int n_gaps_) {
@@ -148,14 +161,16 @@ ym_status Chunk::layout(const int64_t *sdo, const int64_t *tdo, int64_t p0_, int
   row_floats = 0;
   slots = 0;
   n_big = 0;
+  n_big_strips = 0;
   for (int64_t p = p0; p < p1; p++) {
     const int64_t n = sdo[p + 1] - sdo[p], m = tdo[p + 1] - tdo[p];
     if (n > 0 && m > 0) n_items += (n + item_rows - 1) / item_rows;
     cells += n * m;
     s_slots += score_block(n, m);
-    if (nw_needs_global_dirs(n, m)) dir_words += n * nw_dir_row_words(m);
+    dir_words += nw_global_dir_words(n, m);
     row_floats += nw_global_row_floats(n, m);
     if (nw_is_big(n)) n_big++;
+    n_big_strips += nw_tickets(n);
     slots += std::min(n, m);
   }
   // the plan (descriptors, items, move offsets, large-pair list, order) comes
@@ -171,6 +186,10 @@ ym_status Chunk::layout(const int64_t *sdo, const int64_t *tdo, int64_t p0_, int
   o = align256(o + (size_t)std::max<int64_t>(n_big, 1) * 4);
   off_order = o;
   o = align256(o + (size_t)std::max<int64_t>(np, 1) * 4);
+  off_strip0 = o;
+  o = align256(o + (size_t)(n_big + 1) * 4);
+  off_tickets = o;
+  o = align256(o + (size_t)std::max<int64_t>(n_big_strips, 1) * 4);
   host_bytes = o;
   off_S = o;
   o = align256(o + (size_t)s_slots * 4);
@@ -189,6 +208,8 @@ ym_status Chunk::layout(const int64_t *sdo, const int64_t *tdo, int64_t p0_, int
   o = align256(o + G * (size_t)slots * 4);
   off_counts = o;
   o = align256(o + G * (size_t)np * 4);
+  off_ctrl = o;
+  o = align256(o + G * (size_t)(kNwCtrlHead + kNwCtrlPerPair * n_big) * 4);
   bytes = o;
   return YM_OK;
 }
@@ -251,7 +272,7 @@ void Chunk::fill_host(const int64_t *sdo, const int64_t *tdo, char *host) const 
     d.m = (int32_t)m;
     if (nw_needs_global_dirs(n, m)) {
       d.dir_off = dir_off;
-      dir_off += n * nw_dir_row_words(m);
+      dir_off += nw_global_dir_words(n, m);
     } else {
       d.dir_off = -1;
     }
@@ -261,7 +282,6 @@ void Chunk::fill_host(const int64_t *sdo, const int64_t *tdo, char *host) const 
     } else {
       d.row_off = -1;
     }
-    if (nw_is_big(n)) big[nb++] = (int32_t)(p - p0);
     first_item[p - p0] = (int32_t)it;
     if (n > 0 && m > 0) it += (n + item_rows - 1) / item_rows;
     pkey[p - p0] = clamp_key(n * m);
@@ -276,6 +296,19 @@ void Chunk::fill_host(const int64_t *sdo, const int64_t *tdo, char *host) const 
   // items (rows x target sentences) first, so each kernel's last workgroups
   // are short ones
   order_desc(pkey.data(), np, order);
+  // the large pairs in launch order (largest first); their strips' tickets
+  // follow the same order, strip after strip inside a pair
+  int32_t *strip0 = (int32_t *)(host + off_strip0);
+  int32_t *tickets = (int32_t *)(host + off_tickets);
+  int64_t tk = 0;
+  for (int64_t q = 0; q < np; q++) {
+    const int32_t pq = order[q];
+    if (!nw_is_big(descs[pq].n)) continue;
+    strip0[nb] = (int32_t)tk;
+    for (int64_t k = 0; k < nw_tickets(descs[pq].n); k++) tickets[tk++] = (int32_t)nb;
+    big[nb++] = pq;
+  }
+  strip0[nb] = (int32_t)tk;
   std::vector<uint32_t> ikey((size_t)it);
   std::vector<int32_t> ipair((size_t)it), iorder((size_t)it);
   for (int64_t q = 0; q < np; q++) {
@@ -645,9 +678,9 @@ ym_status check_pair_shape(int64_t n, int64_t m, int64_t pair) {
 static size_t pair_plan_bytes(int64_t n, int64_t m) {
   (void)m;
   return sizeof(PairDesc) + (size_t)((n + kMinItemRows - 1) / kMinItemRows) * sizeof(SimItem) + 8 + 4 +
-         (nw_is_big(n) ? 4 : 0);
+         (nw_is_big(n) ? 8 + 4 * nw_tickets(n) : 0);
 }
-static const size_t kPlanSlack = 6 * 256;  // alignment padding of the plan's five regions, and their minimum sizes
+static const size_t kPlanSlack = 8 * 256;  // alignment padding of the plan's seven regions, and their minimum sizes
 
 // Split pairs [0, n_pairs) into chunks whose workspace fits `ws_bytes` and,
 // when `plan_cap` is not 0, whose plan fits `plan_cap` bytes.
@@ -660,7 +693,7 @@ ym_status plan_chunks(const int64_t *sdo, const int64_t *tdo, int64_t n_pairs, s
     if (st) return st;
   }
   while (p < n_pairs) {
-    size_t acc = kChunkSlack, plan = kPlanSlack;
+    size_t acc = chunk_fixed_bytes(n_gaps), plan = kPlanSlack;
     int64_t q = p;
     while (q < n_pairs) {
       const int64_t n = sdo[q + 1] - sdo[q], m = tdo[q + 1] - tdo[q];
@@ -775,6 +808,11 @@ ym_status run_chunk(ym_ctx *c, const ym_lexicon *L, const DevBatch &b, const ym_
   n.n_moves = dbg ? dbg->n_moves_dev : nullptr;
   n.wait_ticks = c->nw_wait_ticks;
   n.status = out.status;
+  n.split = c->nw_large;
+  n.big_strip0 = (const int32_t *)(ws + ch.off_strip0);
+  n.ticket_big = (const int32_t *)(ws + ch.off_tickets);
+  n.n_big_strips = ch.n_big_strips;
+  n.ctrl = (int32_t *)(ws + ch.off_ctrl);
   if (dbg && dbg->gaps) {  // every gap of a sweep in this one launch, outputs per gap
     n.gaps = dbg->gaps;
     n.n_gaps = ch.n_gaps;
@@ -783,6 +821,7 @@ ym_status run_chunk(ym_ctx *c, const ym_lexicon *L, const DevBatch &b, const ym_
     n.g_slots = ch.slots;
     n.g_counts = ch.np;
     n.g_align = dbg->align_stride;
+    n.g_ctrl = kNwCtrlHead + (int64_t)kNwCtrlPerPair * ch.n_big;
   }
   if (n.moves) n.moves += dbg->moves_base;
   {

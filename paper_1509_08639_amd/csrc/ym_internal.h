@@ -38,10 +38,19 @@ static_assert((1 << kLogUcap) == kUcap, "hash capacity");
 // and a row's m cells span at most ceil(m/16) + 1 words.
 __host__ __device__ constexpr int64_t nw_dir_row_words(int64_t m) { return (m + 15) / 16 + 1; }
 
-// Pairs of at least kNwBigStrips strips of 64 rows are swept by a workgroup of
-// kNwBigWaves waves (strips pipelined over the waves); smaller ones by one wave.
+// Pairs of at least kNwBigStrips strips of 64 rows ("large pairs") are swept
+// with their strips pipelined over several waves: either the waves of one
+// kNwBigWaves-wave workgroup per pair, or every wave of a persistent grid
+// (strips taken in dependency order); smaller pairs by one wave each.
 constexpr int kNwBigStrips = 8, kNwBigWaves = 16;
 __host__ __device__ constexpr bool nw_is_big(int64_t n) { return (n + 63) / 64 >= kNwBigStrips; }
+// Persistent-grid sweep of the large pairs: workgroups of four independent
+// waves, at most kNwSplitGroupsPerCu per CU of a 256-CU device.
+constexpr int kNwSplitWaves = 4, kNwSplitGroupsPerCu = 2, kNwSplitCus = 256;
+// Its control words per gap penalty: a ticket counter and the launch's tag,
+// then per large pair {strips finished, give-up flag, H[n][m] and its tag as
+// one 8-byte entry} (an even count, so every entry stays 8-byte aligned).
+constexpr int kNwCtrlHead = 2, kNwCtrlPerPair = 4;
 
 // Score layout of one n x m block: rows in strips of 64 (the last one has
 // R = n - 64 (strips - 1) rows); inside a strip, anti-diagonal t = l + c is a
@@ -147,6 +156,17 @@ struct NwArgs {
   const float *gaps = nullptr;
   int32_t n_gaps = 1;
   int64_t g_dirs = 0, g_rows = 0, g_slots = 0, g_counts = 0, g_align = 0;
+  // Large pairs swept by the persistent grid (split = 1) instead of one
+  // workgroup each: big_strip0[k] is the first ticket of large pair k (its
+  // strips take consecutive tickets; big_strip0[n_big] is the total), ctrl
+  // the control words (kNwCtrlHead + kNwCtrlPerPair * n_big per gap, g_ctrl
+  // apart), and boundary rows hold {H, tag} entries of 8 bytes.
+  int32_t split = 0;
+  const int32_t *big_strip0 = nullptr;
+  const int32_t *ticket_big = nullptr;  // [n_big_strips] large pair (index into big) of each ticket
+  int64_t n_big_strips = 0;
+  int32_t *ctrl = nullptr;
+  int64_t g_ctrl = 0;
 };
 
 // Device status word of a call: 0, or the code of the first device failure.

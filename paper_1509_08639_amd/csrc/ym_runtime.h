@@ -57,9 +57,10 @@ struct DebugOut {
 // Workspace layout of one chunk of pairs [p0, p1).
 struct Chunk {
   int64_t p0 = 0, p1 = 0, np = 0, n_items = 0, cells = 0, s_slots = 0, dir_words = 0, row_floats = 0, slots = 0,
-          n_big = 0;
+          n_big = 0, n_big_strips = 0;
   size_t off_descs = 0, off_items = 0, off_S = 0, off_dirs = 0, off_rows = 0, off_ssrc = 0, off_stgt = 0,
-         off_sscore = 0, off_counts = 0, off_moves_off = 0, off_big = 0, off_order = 0, bytes = 0, host_bytes = 0;
+         off_sscore = 0, off_counts = 0, off_moves_off = 0, off_big = 0, off_order = 0, off_strip0 = 0,
+         off_tickets = 0, off_ctrl = 0, bytes = 0, host_bytes = 0;
   int item_rows = kItemRows;  // source sentences per similarity work item
   int n_gaps = 1;             // copies of the NW regions (gap penalties swept by one NW launch)
   ym_status layout(const int64_t *sdo, const int64_t *tdo, int64_t p0, int64_t p1, int item_rows, int n_gaps = 1);
@@ -70,6 +71,12 @@ ym_status fail(ym_status code, const char *fmt, ...);
 ym_status hip_fail(hipError_t e, const char *what);
 // Workspace bytes of one pair, with the NW outputs and scratch once per gap penalty of a launch.
 size_t pair_bytes(int64_t n, int64_t m, int n_gaps = 1);
+// Workspace bytes of a chunk beyond the pair_bytes of its pairs: the
+// alignment padding of its regions (fewer than 16) and the fixed part of the
+// NW control words.
+inline size_t chunk_fixed_bytes(int n_gaps = 1) {
+  return 16 * 256 + (size_t)(n_gaps > 1 ? n_gaps : 1) * 4 * kNwCtrlHead + 4;
+}
 LexDev lex_dev(const ym_lexicon *L);
 ym_status check_params(const ym_params *p);
 ym_status check_doc_off(const int64_t *o, int64_t n_pairs, const char *what);
@@ -131,6 +138,7 @@ struct ym_ctx {
                         // 3 / 4 bit-sliced tiles of four waves, 1,280- / 2,048-token chunks (=bits / =bits2k)
   int item_rows = ym::kItemRows;  // source sentences per similarity work item
   int nw_pairs_per_group = 1;     // NW workgroup size in pairs (one wave each)
+  int nw_large = 1;               // large pairs: 1 strips over the whole GPU, 0 one workgroup per pair
   uint64_t nw_wait_ticks = ym::kNwWaitTicks;  // limit of one bounded wait of the pipelined sweep
   // kernel timing
   bool prof = false;

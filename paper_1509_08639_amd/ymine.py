@@ -75,10 +75,12 @@ class DeviceOut(C.Structure):
 
 
 class Tuning(C.Structure):
-    _fields_ = [("sim_kernel", C.c_int32), ("item_rows", C.c_int32), ("nw_pairs_per_group", C.c_int32)]
+    _fields_ = [("sim_kernel", C.c_int32), ("item_rows", C.c_int32), ("nw_pairs_per_group", C.c_int32),
+                ("nw_large", C.c_int32)]
 
     def as_dict(self):
-        return dict(sim_kernel=self.sim_kernel, item_rows=self.item_rows, nw_pairs_per_group=self.nw_pairs_per_group)
+        return dict(sim_kernel=self.sim_kernel, item_rows=self.item_rows, nw_pairs_per_group=self.nw_pairs_per_group,
+                    nw_large=self.nw_large)
 
 
 class ServerOpts(C.Structure):
@@ -375,13 +377,14 @@ def set_wait_limit(ctx: Context, ticks: int) -> None:
     _check(lib().ym_set_wait_limit(ctx.h, int(ticks)))
 
 
-def set_tuning(ctx: Context, sim_kernel: int, item_rows: int, nw_pairs_per_group: int):
+def set_tuning(ctx: Context, sim_kernel: int, item_rows: int, nw_pairs_per_group: int, nw_large: int = 1):
     """ym_set_tuning: similarity kernel (1 lanes, 2 lanes with split reads of
     long target sentences, 0 bit-sliced tiles of one wave, 3 / 4 bit-sliced
     tiles of four waves with chunks of 1,280 / 2,048 tokens), source rows per
-    work item (64, 128, 256), NW pairs per workgroup (1, 2, 4).  No choice
-    changes a result."""
-    t = Tuning(sim_kernel, item_rows, nw_pairs_per_group)
+    work item (64, 128, 256), NW pairs per workgroup (1, 2, 4), and the sweep of
+    pairs of 449+ source sentences (1 strips over every CU, 0 one workgroup per
+    pair).  No choice changes a result."""
+    t = Tuning(sim_kernel, item_rows, nw_pairs_per_group, nw_large)
     _check(lib().ym_set_tuning(ctx.h, C.byref(t)))
 
 

@@ -48,6 +48,21 @@ def ctx_k(ym, ctx):
 
 
 @pytest.fixture(scope="module")
+def ctx_large(ym, ctx):
+    """Contexts by sweep of the large pairs (449+ source sentences): 1 strips
+    over every CU (the default context), 0 one 16-wave workgroup per pair."""
+    made = {1: ctx}
+
+    def get(v):
+        if v not in made:
+            c = ym.Context(0)
+            ym.set_tuning(c, 1, 128, 1, v)
+            made[v] = c
+        return made[v]
+    return get
+
+
+@pytest.fixture(scope="module")
 def O():
     return oracle.default()
 
@@ -152,12 +167,37 @@ def _nw_cases():
     return mats
 
 
+@pytest.mark.parametrize("large", [1, 0])
 @pytest.mark.parametrize("gap", [-0.2, -0.25, 0.0, -1.5])
-def test_nw_fed_oracle_scores(ym, ctx, O, gap):
+def test_nw_fed_oracle_scores(ym, ctx_large, O, gap, large):
     mats = _nw_cases()
-    align, moves, res = ym.nw_align(ctx, mats, gap, 0.5)
+    align, moves, res = ym.nw_align(ctx_large(large), mats, gap, 0.5)
     for k, S in enumerate(mats):
         h, mv, _ = O.nw(S, gap)
+        assert align[k].tobytes() == h.tobytes(), (k, S.shape, align[k], h)
+        assert moves[k] == mv, (k, S.shape)
+        si, ti, sc = O.emit(S, mv, 0.5)
+        gp, gs = parity.pairs_of(res, k)
+        assert gp == list(zip(si.tolist(), ti.tolist())), k
+        assert gs.tobytes() == sc.tobytes(), k
+
+
+@pytest.mark.parametrize("large", [1, 0])
+def test_nw_many_large_pairs(ym, ctx_large, O, large):
+    """More strips of large pairs than the persistent grid has waves (so waves
+    take several tickets), pairs of 8 to 10 strips with 0 to 40 target
+    sentences, in both sweeps of the large pairs, against the oracle."""
+    r = np.random.default_rng(77)
+    mats = []
+    for k in range(270):
+        n = int(r.integers(449, 641))
+        m = int(r.integers(0, 41)) if k % 9 else int(k % 2)
+        mats.append(r.random((n, m)).astype(np.float32))
+    mats.append((r.integers(0, 3, (520, 33)) / 4.0).astype(np.float32))  # dyadic ties
+    assert sum((S.shape[0] + 63) // 64 for S in mats) > 2048
+    align, moves, res = ym.nw_align(ctx_large(large), mats, -0.2, 0.5)
+    for k, S in enumerate(mats):
+        h, mv, _ = O.nw(S, F32(-0.2))
         assert align[k].tobytes() == h.tobytes(), (k, S.shape, align[k], h)
         assert moves[k] == mv, (k, S.shape)
         si, ti, sc = O.emit(S, mv, 0.5)
@@ -237,6 +277,25 @@ def test_mine_ragged_edges_end_to_end(ym, ctx, O):
     S, _, _ = ym.similarity(ctx, L, c, w)
     ties = parity.compare_mined(O, OL, c, w, F32(-0.2), F32(0.5), got, want, S)
     parity.assert_ties("ragged_30_pairs_seed4", ties)
+
+
+@pytest.mark.parametrize("large", [1, 0])
+def test_mine_large_pairs_end_to_end(ym, ctx_large, O, large):
+    """A batch mixing pairs of 449+ source sentences with small ones, end to
+    end in both sweeps of the large pairs, against the oracle."""
+    lex = parity.random_lexicon(11)
+    c = parity.random_corpus(11, n_pairs=8, nmax=760, mmax=130, lmax_src=12, lmax_tgt=12)
+    n, _ = c.nm()
+    assert (n >= 449).sum() >= 2
+    w = np.array([-1.5, 3.0, 2.0, 0.5], np.float32)
+    cx = ctx_large(large)
+    L = cx.lexicon(lex.src_ids, lex.off, lex.tgt_ids)
+    got = ym.mine(cx, L, c, w, -0.2, 0.5)
+    OL = O.lexicon(lex.src_ids, lex.off, lex.tgt_ids)
+    want = O.mine(OL, c, w, -0.2, 0.5)
+    S, _, _ = ym.similarity(cx, L, c, w)
+    ties = parity.compare_mined(O, OL, c, w, F32(-0.2), F32(0.5), got, want, S)
+    parity.assert_ties("large_pairs_8_seed11", ties)
 
 
 def test_long_pair(ym, ctx, O):
@@ -416,13 +475,15 @@ def test_served_tail_pair_4000x4000(ym, ctx, O):
     parity.compare_result_fields(r, got, "served 4000 x 4000")
 
 
-def test_pipelined_sweep_give_up_is_an_error(ym, O):
+@pytest.mark.parametrize("large", [1, 0])
+def test_pipelined_sweep_give_up_is_an_error(ym, O, large):
     """A bounded wait of the pipelined sweep that gives up (forced from the
     host: a zero wait limit makes every such wait give up at once, and every
     kernel still runs to its end) fails the call with YM_EDEVICE; pairs that
     do not need the pipelined sweep are not affected, and the default limit
-    restores normal results."""
+    restores normal results.  Both sweeps of the large pairs."""
     ctx = ym.Context(0)
+    ym.set_tuning(ctx, 1, 128, 1, large)
     r = np.random.default_rng(31)
     big = [r.random((700, 90)).astype(np.float32)]
     small = [r.random((60, 70)).astype(np.float32)]

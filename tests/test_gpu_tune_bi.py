@@ -136,6 +136,31 @@ def test_tune_small_workspace_and_edges(ym, ctx, O):
         ym.tune(ctx, L, c, w, np.array([np.nan], np.float32), taus, c.truth_off, c.truth_src, c.truth_tgt)
 
 
+@pytest.mark.parametrize("large", [1, 0])
+def test_tune_gaps_in_one_launch_with_large_pairs(ym, O, large):
+    """Several gap penalties swept in one NW launch over a batch holding pairs
+    of 449+ source sentences, in both sweeps of the large pairs: every gap's
+    counts equal those of a plain mining run at that gap."""
+    ctx = ym.Context(0)
+    ym.set_tuning(ctx, 1, 128, 1, large)
+    lex = parity.random_lexicon(11)
+    c = parity.random_corpus(11, n_pairs=8, nmax=760, mmax=130, lmax_src=12, lmax_tgt=12)
+    n, m = c.nm()
+    k = np.minimum(n, m)
+    c.truth_off = np.concatenate([[0], np.cumsum(k)]).astype(np.int64)
+    c.truth_src = np.concatenate([np.arange(x) for x in k] + [np.zeros(0)]).astype(np.int32)
+    c.truth_tgt = c.truth_src.copy()
+    w = np.array([-1.5, 3.0, 2.0, 0.5], np.float32)
+    L = ctx.lexicon(lex.src_ids, lex.off, lex.tgt_ids)
+    S, _, _ = ym.similarity(ctx, L, c, w)
+    gaps = np.array([-0.2, -0.5, 0.0], np.float32)
+    taus = _away_from(S, [0.3, 0.5, 0.7])
+    nm, nc = ym.tune(ctx, L, c, w, gaps, taus, c.truth_off, c.truth_src, c.truth_tgt)
+    for gi, g in enumerate(gaps):
+        gm, gc = _counts(ym.mine(ctx, L, c, w, g, -1.0), c, taus)
+        assert np.array_equal(nm[gi], gm) and np.array_equal(nc[gi], gc), gi
+
+
 def _reverse_lexicon(lex):
     """The lexicon read the other way: every (x, y) entry becomes (y, x)."""
     pairs = sorted({(int(y), int(x)) for k, x in enumerate(lex.src_ids)

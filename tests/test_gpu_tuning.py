@@ -39,7 +39,7 @@ def test_every_configuration_gives_the_same_result(ym):
     c = parity.random_corpus(21, n_pairs=24, nmax=300, mmax=150, lmax_src=40, lmax_tgt=45)
     w = np.array([-1.5, 3.0, 2.0, 0.5], np.float32)
     L = ctx.lexicon(lex.src_ids, lex.off, lex.tgt_ids)
-    assert ym.get_tuning(ctx) == dict(sim_kernel=1, item_rows=128, nw_pairs_per_group=1)
+    assert ym.get_tuning(ctx) == dict(sim_kernel=1, item_rows=128, nw_pairs_per_group=1, nw_large=1)
     ref = ym.mine(ctx, L, c, w, -0.2, 0.5)
     S_ref, ms_ref, mt_ref = ym.similarity(ctx, L, c, w)
     OL = oracle.default().lexicon(lex.src_ids, lex.off, lex.tgt_ids)
@@ -51,7 +51,7 @@ def test_every_configuration_gives_the_same_result(ym):
     dm = ym.DeviceMiner(ctx, L, c)
     for sk, rows, ppg in CONFIGS:
         ym.set_tuning(ctx, sk, rows, ppg)
-        assert ym.get_tuning(ctx) == dict(sim_kernel=sk, item_rows=rows, nw_pairs_per_group=ppg)
+        assert ym.get_tuning(ctx) == dict(sim_kernel=sk, item_rows=rows, nw_pairs_per_group=ppg, nw_large=1)
         _same(ref, ym.mine(ctx, L, c, w, -0.2, 0.5))
         dm.run(w, -0.2, 0.5)
         _same(ref, dm.result())
@@ -61,10 +61,11 @@ def test_every_configuration_gives_the_same_result(ym):
 
 def test_set_tuning_rejects_other_values(ym):
     ctx = ym.Context(0)
-    for bad in [(5, 128, 1), (-1, 128, 1), (1, 96, 1), (1, 512, 1), (1, 128, 3), (0, 128, 8)]:
+    for bad in [(5, 128, 1), (-1, 128, 1), (1, 96, 1), (1, 512, 1), (1, 128, 3), (0, 128, 8), (1, 128, 1, 2),
+                (1, 128, 1, -1)]:
         with pytest.raises(ym.YmError):
             ym.set_tuning(ctx, *bad)
-    assert ym.get_tuning(ctx) == dict(sim_kernel=1, item_rows=128, nw_pairs_per_group=1)
+    assert ym.get_tuning(ctx) == dict(sim_kernel=1, item_rows=128, nw_pairs_per_group=1, nw_large=1)
 
 
 def test_autotune_applies_a_valid_configuration(ym):
@@ -77,6 +78,7 @@ def test_autotune_applies_a_valid_configuration(ym):
     ref = ym.mine(ctx, L, c, w, -0.2, 0.5)
     best, ms = ym.autotune(ctx, L, c, w, -0.2, 0.5, reps=2)
     assert (best["sim_kernel"], best["item_rows"], best["nw_pairs_per_group"]) in CONFIGS
+    assert best["nw_large"] in (0, 1)
     assert ms > 0
     assert ym.get_tuning(ctx) == best
     _same(ref, ym.mine(ctx, L, c, w, -0.2, 0.5))
