@@ -2156,18 +2156,18 @@ __device__ __forceinline__ bool nw_wait(const NwPipe &pp, int strip, int cols) {
 }
 
 // Entry t of the previous strip's bottom row in the persistent-grid sweep,
-// for the lanes with `need`.  Entries are 8 bytes, {H, tag}, stored with one
-// atomic store by the wave of that strip (possibly on another CU or XCD): an
-// entry carrying this launch's tag holds this launch's value, so no flag or
-// fence is needed.  The wave waits until every needed entry has the tag, for
-// at most the time limit; a give-up (or an earlier one for the same pair)
-// sets the pair's flag, and the sweep goes on with whatever the entries hold.
-__device__ __forceinline__ float nw_row_take(const NwPipe &pp, const uint64_t *row, int t, bool need) {
+// for the lanes with `need`, given v, that entry as loaded one block earlier.
+// Entries are 8 bytes, {H, tag}, stored with one atomic store by the wave of
+// that strip (possibly on another CU or XCD): an entry carrying this launch's
+// tag holds this launch's value, so no flag or fence is needed.  The wave
+// reads the entries again until every needed one has the tag, for at most the
+// time limit; a give-up (or an earlier one for the same pair) sets the pair's
+// flag, and the sweep goes on with whatever the entries hold.
+__device__ __forceinline__ float nw_row_take(const NwPipe &pp, const uint64_t *row, int t, bool need, uint64_t v) {
   if (pp.limit == 0) {  // failure injection: every wait gives up
     if ((threadIdx.x & 63) == 0) __hip_atomic_store(pp.gabort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return 0.0f;
   }
-  uint64_t v = need ? __hip_atomic_load(row + t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0ull;
   bool ok = !need || (uint32_t)(v >> 32) == pp.tag;
   if (__builtin_expect(__ballot(!ok) != 0ull, 0)) {
     const uint64_t t0 = wall_clock64();
@@ -2204,14 +2204,24 @@ __device__ __forceinline__ void nw_publish(const NwPipe &pp, int strip, int cols
 // first or after its last slot return 0 without touching memory; the values
 // of lanes outside a diagonal are never used.  For strips after the first,
 // lane k also fetches the previous strip's bottom-row value H[64s][t] of the
-// block's step k (handed to lane 0 by readlane).
+// block's step k (handed to lane 0 by readlane).  In the persistent-grid
+// sweep those entries were loaded one block earlier (pend) and are checked
+// here, and the next block's are loaded, so a round trip to another CU's
+// writes overlaps a block of steps.
 template <bool kTagged>
 __device__ __forceinline__ void nw_prefetch(float (&buf)[kNwUnroll], float &rbv, __amdgpu_buffer_rsrc_t rs,
                                             const float *rowbuf, bool use_row, int &d, int lane, int R, int m,
-                                            const NwPipe &pp, int s) {
+                                            const NwPipe &pp, int s, uint64_t &pend) {
   const int t = d + 1 + lane;
   if (kTagged) {
-    rbv = use_row ? nw_row_take(pp, (const uint64_t *)rowbuf, t, lane < kNwUnroll && t <= m) : 0.0f;
+    rbv = 0.0f;
+    if (use_row) {
+      const uint64_t *row = (const uint64_t *)rowbuf;
+      rbv = nw_row_take(pp, row, t, lane < kNwUnroll && t <= m, pend);
+      const int tn = t + kNwUnroll;
+      pend = (lane < kNwUnroll && tn <= m) ? __hip_atomic_load(row + tn, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                            : 0ull;
+    }
   } else {
     if (pp.prog && use_row) nw_wait(pp, s - 1, min(m, d + kNwUnroll) + 1);
     rbv = (use_row && lane < kNwUnroll && t <= m) ? rowbuf[t] : 0.0f;
@@ -2330,16 +2340,20 @@ __device__ __forceinline__ float nw_strip(const NwArgs &a, const PairDesc &d, in
   float bufA[kNwUnroll], bufB[kNwUnroll], rbA, rbB;
   int cd = -1;  // prefetch cursor: step t reads diagonal t-1
   const bool use_row = s > 0;
-  nw_prefetch<kTagged>(bufA, rbA, rs, rowin, use_row, cd, lane, R, m, pp, s);
+  // persistent-grid sweep: the first block's boundary-row entries, in flight
+  uint64_t pend = 0;
+  if (kTagged && use_row && lane < kNwUnroll && lane <= m)
+    pend = __hip_atomic_load((const uint64_t *)rowin + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  nw_prefetch<kTagged>(bufA, rbA, rs, rowin, use_row, cd, lane, R, m, pp, s, pend);
   int t0 = 0;
   // full blocks of 2 x 16 steps
   for (; t0 + 2 * kNwUnroll - 1 <= tend; t0 += 2 * kNwUnroll) {
-    nw_prefetch<kTagged>(bufB, rbB, rs, rowin, use_row, cd, lane, R, m, pp, s);
+    nw_prefetch<kTagged>(bufB, rbB, rs, rowin, use_row, cd, lane, R, m, pp, s, pend);
     if (s == 0)
       nw_steps<false, true, kTagged>(bufA, rbA, t0, tend, L, lane, i, rowok, lastlane, keep_row, m, Wr, g, dirs, rowout, pp, s);
     else
       nw_steps<false, false, kTagged>(bufA, rbA, t0, tend, L, lane, i, rowok, lastlane, keep_row, m, Wr, g, dirs, rowout, pp, s);
-    nw_prefetch<kTagged>(bufA, rbA, rs, rowin, use_row, cd, lane, R, m, pp, s);
+    nw_prefetch<kTagged>(bufA, rbA, rs, rowin, use_row, cd, lane, R, m, pp, s, pend);
     if (s == 0)
       nw_steps<false, true, kTagged>(bufB, rbB, t0 + kNwUnroll, tend, L, lane, i, rowok, lastlane, keep_row, m, Wr, g, dirs,
                             rowout, pp, s);
@@ -2353,7 +2367,7 @@ __device__ __forceinline__ float nw_strip(const NwArgs &a, const PairDesc &d, in
       nw_steps<true, true, kTagged>(bufA, rbA, t0, tend, L, lane, i, rowok, lastlane, keep_row, m, Wr, g, dirs, rowout, pp, s);
     else
       nw_steps<true, false, kTagged>(bufA, rbA, t0, tend, L, lane, i, rowok, lastlane, keep_row, m, Wr, g, dirs, rowout, pp, s);
-    if (t0 + kNwUnroll <= tend) nw_prefetch<kTagged>(bufA, rbA, rs, rowin, use_row, cd, lane, R, m, pp, s);
+    if (t0 + kNwUnroll <= tend) nw_prefetch<kTagged>(bufA, rbA, rs, rowin, use_row, cd, lane, R, m, pp, s, pend);
   }
   return __shfl(L.h, lastlane);
 }
