@@ -325,7 +325,7 @@ def main():
     ap.add_argument("--tuning", type=str, default="",
                     help="fixed launch configuration 'sim_kernel,item_rows,nw_pairs_per_group,nw_large' "
                          "for every leg instead of the autotuner's choices (profiling runs)")
-    ap.add_argument("--autotune-pairs", type=int, default=20000,
+    ap.add_argument("--autotune-pairs", type=int, default=100000,
                     help="pairs of the autotuner's sample, spread over the batch (0: default configuration)")
     ap.add_argument("--workspace-gib", type=float, default=64.0, help="workspace cap of the device form (GiB)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
