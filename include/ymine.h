@@ -327,8 +327,9 @@ ym_status ym_get_tuning(ym_ctx *ctx, ym_tuning *tuning);
  * after one untimed pass, first over the fifteen (sim_kernel, item_rows) pairs,
  * then over the NW workgroup sizes with the best of them, then (when the
  * sample holds a pair of 449 or more source sentences) both nw_large, compared
- * on the NW kernels' own time (unless kernel timing is enabled on the context,
- * whose events it would consume: then on whole passes).  The fastest
+ * on the NW kernels' own time (unless kernel timing is enabled on the context
+ * or holds events not read yet, which it would consume: then on whole
+ * passes).  The fastest
  * configuration is applied to the context and returned in *best, its mean
  * time per pass in *best_ms (may be NULL).  On error the previous
  * configuration is kept. */

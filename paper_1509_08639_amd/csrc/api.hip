@@ -733,10 +733,10 @@ ym_status ym_autotune(ym_ctx *c, const ym_lexicon *L, const ym_batch *b, const y
   // sweeps differ only in the NW launches, a small part of a pass, so they
   // are compared on the NW kernels' own time (HIP events around the NW
   // launches), unless the caller is collecting kernel timings itself.
-  bool user_prof = false;
+  bool user_prof = false;  // the caller's timing is on, or has events not read yet
   {
     std::lock_guard<std::mutex> pl(c->prof_mu);
-    user_prof = c->prof;
+    user_prof = c->prof || !c->ev_pending.empty();
   }
   if (!s && has_big && user_prof) {
     const ym_tuning t{win.sim_kernel, win.item_rows, win.nw_pairs_per_group, 1 - win.nw_large};
