@@ -1516,7 +1516,10 @@ __global__ __launch_bounds__(kTileThreads) void sim_tile_kernel(SimArgs a) {
 // through LDS, the m_s planes transposed (lane = sentence), and each wave
 // scores a quarter of the tile's rows from the score table.  Tiles whose
 // sentences exceed 63 tokens (counts need 11 planes) run both passes on one
-// wave and score cell by cell.
+// wave and score cell by cell.  A workgroup takes a work item (a pair's rows,
+// at most four strips) chunk by chunk: the hash and D of a chunk are built
+// once and kept while each of the item's strips is counted against it, with
+// B and the counter exchange sharing one region that is cleared per strip.
 constexpr int kBitsWaves = 4;
 constexpr int kBitsThreads = 64 * kBitsWaves;
 constexpr int kBitsNarrow = 6;  // planes for counts <= 63
@@ -1533,24 +1536,25 @@ struct BitsHash {
 };
 template <int TC>
 struct BitsLds {
-  // region H: the chunk's id hash (TC buckets of two {key, local id} slots);
-  // once the source pass is done, the partial counters of the waves
+  // the chunk's id hash (TC buckets of two {key, local id} slots) and D (id 0:
+  // none, always 0; one spare entry): built once per chunk, read by every
+  // strip of the item
+  __align__(16) int2 ent[2 * BitsHash<TC>::kNB];
+  __align__(16) uint64_t D[TC + 2];
+  // region W, per strip: B during the two passes (with one spare entry per
+  // lane after the ids, the target of the lanes whose id is not in the
+  // chunk), then the waves' partial counters and the summed and transposed
+  // ones, then the tile's scores (row r, chunk sentence j at j + 66 r: both
+  // the writes by sentence and the reads by anti-diagonal are free of bank
+  // conflicts); while a chunk is staged, the sentence of each staged position
   union {
-    __align__(16) int2 ent[2 * BitsHash<TC>::kNB];
+    uint64_t B[TC + 2 + 64];
     uint64_t xch[2 * (kBitsWaves - 1) * kBitsNarrow * 64];
-  } h;
-  // region DB: D and B (id 0: none, always 0; one spare entry); once the
-  // target pass is done, the summed m_s
-  // (row-major), the transposed m_s and m_t (lane = sentence)
-  union {
-    struct {
-      uint64_t D[TC + 2];
-      uint64_t B[TC + 2];
-    } db;
-    uint64_t fin[3 * kBitsWide * 64];
-  } d;
+    uint64_t fin[2 * kBitsWide * 64];
+    float stage[66 * 64];
+    uint8_t tsen[TC + 3 * kJcap];
+  } w;
   __align__(16) uint16_t tdoc[TC + 3 * kJcap];  // local ids, each sentence padded to a multiple of 4 (id 0)
-  uint8_t tsen[TC + 3 * kJcap];                  // sentence of each staged position
   uint16_t toff[kJcap], toff_o[kJcap + 1], tlen[kJcap];
   int ends[kJcap];
   int j1, nlid, npad, bmax;
@@ -1600,12 +1604,15 @@ __device__ __forceinline__ void bits_find(const int4 *ent4, const int32_t (&x)[K
     b[k] = bits_bucket<NB>(x[k]);
     e[k] = ent4[b[k]];
   }
+  // Branch-free on the first round: a key sits in at most one slot, and a
+  // search for x < 0 gets 0 (an empty slot's id word is 0, and only a full
+  // bucket carries the mark).
   uint32_t pend = 0;
 #pragma unroll
   for (int k = 0; k < K; k++) {
-    lid[k] = (x[k] >= 0 && e[k].x == x[k]) ? (e[k].y & kBitsIdMask)
-           : (x[k] >= 0 && e[k].z == x[k]) ? (e[k].w & kBitsIdMask) : 0;
-    pend |= (uint32_t)(x[k] >= 0 && lid[k] == 0 && (e[k].w & kBitsOverflow) != 0) << k;
+    const uint32_t v = (e[k].x == x[k] ? (uint32_t)e[k].y : 0u) | (e[k].z == x[k] ? (uint32_t)e[k].w : 0u);
+    lid[k] = (int)(v & kBitsIdMask);
+    pend |= (uint32_t)((x[k] >= 0) & (lid[k] == 0) & ((e[k].w & kBitsOverflow) != 0)) << k;
   }
   while (pend) {
 #pragma unroll
@@ -1676,34 +1683,38 @@ __device__ __forceinline__ void bits_chunk_end(const int64_t *toffs, int j0, int
   ends[lane] = (int)clamp64(e, 0, 1 << 30);
 }
 
+// Translation records of iteration u of the source pass (below): positions
+// q = q0 + qs (NR u + k) of this lane's row, {-1, -1, -1, -1} past its end.
+template <int NR>
+__device__ __forceinline__ void bits_s_fetch(const SimArgs &a, int64_t sb, int al, int q0, int qs, int u,
+                                             int4 (&r)[NR]) {
+#pragma unroll
+  for (int k = 0; k < NR; k++) {
+    const int q = q0 + qs * (NR * u + k);
+    r[k] = q < al ? a.trans[sb + q] : make_int4(-1, -1, -1, -1);
+  }
+}
+
 // Source pass over the positions q = q0 + qs (4 G u + k) of this lane's row
 // (record base sb, length al; amax: the longest row of the strip): marks B and
 // adds, per position, the set of the chunk's sentences meeting its
 // translations into the planes (lo: sentences 0-31, hi: 32-63).  G groups of
-// four positions per iteration (their lookups overlap); the next iteration's
-// records are fetched while this one is worked on.
+// four positions per iteration (their lookups overlap); ra holds the first
+// iteration's records (fetched by the caller), and the next iteration's are
+// fetched while one is worked on.
 template <int NPL, int TC, int G>
 __device__ __forceinline__ void bits_s_pass(const SimArgs &a, BitsLds<TC> &L, int64_t sb, int al, int amax, int q0,
-                                            int qs, uint32_t (&lo)[NPL], uint32_t (&hi)[NPL]) {
+                                            int qs, int4 (&ra)[4 * G], uint32_t (&lo)[NPL], uint32_t (&hi)[NPL]) {
   constexpr uint32_t HB = BitsHash<TC>::kNB;  // buckets of two slots
   constexpr int NR = 4 * G;                   // records per iteration
-  const int4 *ent4 = reinterpret_cast<const int4 *>(L.h.ent);
+  const int4 *ent4 = reinterpret_cast<const int4 *>(L.ent);
   const int lane = threadIdx.x & 63;
   const unsigned long long rowbit = 1ull << lane;
-  unsigned long long *B = reinterpret_cast<unsigned long long *>(L.d.db.B);
-  const uint64_t *D = L.d.db.D;
-  auto fetch = [&](int u, int4 (&r)[NR]) {
-#pragma unroll
-    for (int k = 0; k < NR; k++) {
-      const int q = q0 + qs * (NR * u + k);
-      r[k] = q < al ? a.trans[sb + q] : make_int4(-1, -1, -1, -1);
-    }
-  };
-  int4 ra[NR];
-  fetch(0, ra);
+  unsigned long long *B = reinterpret_cast<unsigned long long *>(L.w.B);
+  const uint64_t *D = L.D;
   for (int u = 0; q0 + qs * NR * u < amax; u++) {
     int4 rb[NR];
-    fetch(u + 1, rb);
+    bits_s_fetch<NR>(a, sb, al, q0, qs, u + 1, rb);
     bool far = false;
     uint64_t c[NR];
 #pragma unroll
@@ -1721,11 +1732,10 @@ __device__ __forceinline__ void bits_s_pass(const SimArgs &a, BitsLds<TC> &L, in
       }
       int lid[8];
       bits_find<HB>(ent4, x, lid);
-      // only ids of the chunk are marked (most translations miss it; marking
-      // the misses in one shared slot would serialise the atomics)
+      // ids not in the chunk are marked in the lane's own spare entry (one
+      // shared slot would serialise the atomics), so no lane branches
 #pragma unroll
-      for (int k = 0; k < 8; k++)
-        if (lid[k]) atomicOr(&B[lid[k]], rowbit);
+      for (int k = 0; k < 8; k++) atomicOr(&B[lid[k] ? lid[k] : TC + 2 + lane], rowbit);
 #pragma unroll
       for (int k = 0; k < 2; k++)
         c[2 * hf + k] = (D[lid[4 * k]] | D[lid[4 * k + 1]]) | (D[lid[4 * k + 2]] | D[lid[4 * k + 3]]);
@@ -1762,7 +1772,7 @@ __device__ __forceinline__ void bits_t_pass(const BitsLds<TC> &L, int nj, int k0
   const bool jok = j < nj;
   const int bl = jok ? L.tlen[j] : 0;
   const uint16_t *tp = L.tdoc + (jok ? L.toff[j] : 0);
-  const uint64_t *B = L.d.db.B;
+  const uint64_t *B = L.w.B;
   const int bmax = L.bmax;
   for (int k = k0; k < bmax; k += 2 * ks) {
     uint64_t x[8];
@@ -1846,14 +1856,14 @@ __device__ __forceinline__ void bits_load(const uint64_t *src, uint32_t (&lo)[NP
 
 template <int TC>
 __global__ __launch_bounds__(kBitsThreads, TC <= 1280 ? 3 : 2) void sim_bits_kernel(SimArgs a) {
+  static_assert(kMaxItemRows <= 4 * 64, "an item's rows are kept for at most four strips");
   __shared__ BitsLds<TC> L;
   constexpr uint32_t NS = 2 * BitsHash<TC>::kNB;  // hash slots
   constexpr int kTpt = (TC + kBitsThreads - 1) / kBitsThreads;  // staged tokens per thread
+  constexpr int NR = 4 * BitsHash<TC>::kGroups;                 // source records per pass iteration
+  constexpr int kPl = kBitsNarrow * 64;                         // one set of narrow planes in W
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-  uint64_t *const comb_s = L.d.fin;                  // summed m_s, lane = row
-  uint64_t *const fin_s = L.d.fin + kBitsWide * 64;  // m_s, lane = sentence
-  uint64_t *const fin_t = L.d.fin + 2 * kBitsWide * 64;
 
   for (int64_t item = blockIdx.x; item < a.n_items; item += gridDim.x) {
     const SimItem it = a.items[item];
@@ -1861,117 +1871,146 @@ __global__ __launch_bounds__(kBitsThreads, TC <= 1280 ? 3 : 2) void sim_bits_ker
     if (m <= 0 || it.i1 <= it.i0) continue;
     const int64_t *toffs = a.tgt_sent_off + it.tgt_sent0;
     const int64_t *soffs = a.src_sent_off + it.src_sent0;
-    for (int r0 = it.i0; r0 < it.i1; r0 += 64) {  // the item's strips (items start on a strip)
-      const int R = min(64, n - r0);
-      float *const strip = a.S + it.s_off + (int64_t)(r0 >> 6) * (m + 63) * 64;
-      // this lane's row (every wave holds the strip's rows in the same lanes)
-      int64_t sb = 0;
-      int al = 0;
-      if (lane < R) {
-        sb = clamp64(soffs[r0 + lane], 0, a.n_src_tok);
-        al = (int)min(clamp64(soffs[r0 + lane + 1], sb, a.n_src_tok) - sb, (int64_t)0x7fffffff);
+    // this lane's row of each of the item's strips (every wave holds a strip's
+    // rows in the same lanes); items start on a strip and span at most four
+    int64_t sbv[4];
+    int alv[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      const int r = it.i0 + 64 * k + lane;
+      sbv[k] = 0;
+      alv[k] = 0;
+      if (r < it.i1) {
+        sbv[k] = clamp64(soffs[r], 0, a.n_src_tok);
+        alv[k] = (int)min(clamp64(soffs[r + 1], sbv[k], a.n_src_tok) - sbv[k], (int64_t)0x7fffffff);
       }
-      const int amax = __builtin_amdgcn_readfirstlane(wave_max(al));
+    }
 
-      for (int j0 = 0; j0 < m;) {
-        // ---- stage the chunk: ids -> local ids, sentences, D ----
-        if (tid < 64) bits_chunk_end<TC>(toffs, j0, m, a.n_tgt_tok, &L.j1, L.ends);
-        if (tid == 0) L.nlid = 0;
-        {  // 16-byte stores: the hash to {empty, 0}, D and B to 0
-          int4 *e4 = reinterpret_cast<int4 *>(L.h.ent);
-          for (int s = tid; s < (int)NS / 2; s += kBitsThreads) e4[s] = make_int4(kEmpty, 0, kEmpty, 0);
-          uint4 *d4 = reinterpret_cast<uint4 *>(&L.d.db);
-          for (int s = tid; s < TC + 2; s += kBitsThreads) d4[s] = make_uint4(0u, 0u, 0u, 0u);
-        }
-        __syncthreads();
-        const int j1 = L.j1, nj = j1 - j0;
-        const int64_t tbase = clamp64(toffs[j0], 0, a.n_tgt_tok);
-        const int ntok = min(L.ends[nj - 1], TC);
-        int32_t xs[kTpt];
+    for (int j0 = 0; j0 < m;) {
+      // ---- stage the chunk once for all of the item's strips: ids -> local ids, sentences, D ----
+      if (tid < 64) bits_chunk_end<TC>(toffs, j0, m, a.n_tgt_tok, &L.j1, L.ends);
+      if (tid == 0) L.nlid = 0;
+      {  // 16-byte stores: the hash to {empty, 0}, D to 0
+        int4 *e4 = reinterpret_cast<int4 *>(L.ent);
+        for (int s = tid; s < (int)NS / 2; s += kBitsThreads) e4[s] = make_int4(kEmpty, 0, kEmpty, 0);
+        uint4 *d4 = reinterpret_cast<uint4 *>(L.D);
+        for (int s = tid; s < (TC + 2) / 2; s += kBitsThreads) d4[s] = make_uint4(0u, 0u, 0u, 0u);
+      }
+      __syncthreads();
+      const int j1 = L.j1, nj = j1 - j0;
+      const int64_t tbase = clamp64(toffs[j0], 0, a.n_tgt_tok);
+      const int ntok = min(L.ends[nj - 1], TC);
+      int32_t xs[kTpt];
 #pragma unroll
-        for (int u = 0; u < kTpt; u++) {
-          const int p = tid + kBitsThreads * u;
-          xs[u] = p < ntok ? a.tgt_tok[tbase + p] : -1;
+      for (int u = 0; u < kTpt; u++) {
+        const int p = tid + kBitsThreads * u;
+        xs[u] = p < ntok ? a.tgt_tok[tbase + p] : -1;
+      }
+      if (tid < 64) {  // sentence layout by one wave-wide scan
+        int ostart = 0, blen = 0;
+        if (lane < nj) {
+          ostart = lane == 0 ? 0 : min(L.ends[lane - 1], ntok);
+          blen = min(max(L.ends[lane], ostart), ntok) - ostart;
         }
-        if (tid < 64) {  // sentence layout by one wave-wide scan
-          int ostart = 0, blen = 0;
-          if (lane < nj) {
-            ostart = lane == 0 ? 0 : min(L.ends[lane - 1], ntok);
-            blen = min(max(L.ends[lane], ostart), ntok) - ostart;
-          }
-          const int plen = (blen + 3) & ~3;
-          int x = plen;
+        const int plen = (blen + 3) & ~3;
+        int x = plen;
 #pragma unroll
-          for (int o = 1; o < 64; o <<= 1) {
-            const int y = __shfl_up(x, o);
-            if (lane >= o) x += y;
-          }
-          const int pstart = x - plen;
-          if (lane < nj) {
-            L.toff_o[lane] = (uint16_t)ostart;
-            L.tlen[lane] = (uint16_t)blen;
-            L.toff[lane] = (uint16_t)pstart;
-            for (int q = blen; q < plen; q++) L.tdoc[pstart + q] = 0xFFFF;
-          }
-          if (lane == 0) L.toff_o[nj] = (uint16_t)ntok;
-          if (lane == 63) L.npad = x;
-          const int bm = wave_max(blen);
-          if (lane == 0) L.bmax = bm;
+        for (int o = 1; o < 64; o <<= 1) {
+          const int y = __shfl_up(x, o);
+          if (lane >= o) x += y;
         }
-        __syncthreads();
-        // every token into the hash; a key new to the chunk takes the next local id
+        const int pstart = x - plen;
+        if (lane < nj) {
+          L.toff_o[lane] = (uint16_t)ostart;
+          L.tlen[lane] = (uint16_t)blen;
+          L.toff[lane] = (uint16_t)pstart;
+          for (int q = blen; q < plen; q++) L.tdoc[pstart + q] = 0xFFFF;
+        }
+        if (lane == 0) L.toff_o[nj] = (uint16_t)ntok;
+        if (lane == 63) L.npad = x;
+        const int bm = wave_max(blen);
+        if (lane == 0) L.bmax = bm;
+      }
+      __syncthreads();
+      // every token into the hash; a key new to the chunk takes the next local id
 #pragma unroll
-        for (int u = 0; u < kTpt; u++) {
-          const int p = tid + kBitsThreads * u;
-          bool fresh = false;
-          int h = 0xFFFF;
-          if (p < ntok) {
-            int lo = 0;  // sentence holding token p: the last start <= p
+      for (int u = 0; u < kTpt; u++) {
+        const int p = tid + kBitsThreads * u;
+        bool fresh = false;
+        int h = 0xFFFF;
+        if (p < ntok) {
+          int lo = 0;  // sentence holding token p: the last start <= p
 #pragma unroll
-            for (int step = kJcap / 2; step >= 1; step >>= 1)
-              if (lo + step < nj && L.toff_o[lo + step] <= p) lo += step;
-            const int dst = L.toff[lo] + (p - L.toff_o[lo]);
-            if (xs[u] >= 0) h = bits_insert<BitsHash<TC>::kNB>(L.h.ent, xs[u], fresh);
-            L.tdoc[dst] = (uint16_t)h;
-            L.tsen[dst] = (uint8_t)lo;
-          }
-          const uint64_t nb = __ballot(fresh);
-          if (nb) {
-            const int lead = __builtin_ctzll(nb);
-            int base = 0;
-            if (lane == lead) base = atomicAdd(&L.nlid, __popcll(nb));
-            base = __builtin_amdgcn_readlane(base, lead);
-            if (fresh) atomicOr(&L.h.ent[h].y, 1 + base + __popcll(nb & ((1ull << lane) - 1)));  // keeps a mark
-          }
+          for (int step = kJcap / 2; step >= 1; step >>= 1)
+            if (lo + step < nj && L.toff_o[lo + step] <= p) lo += step;
+          const int dst = L.toff[lo] + (p - L.toff_o[lo]);
+          if (xs[u] >= 0) h = bits_insert<BitsHash<TC>::kNB>(L.ent, xs[u], fresh);
+          L.tdoc[dst] = (uint16_t)h;
+          L.w.tsen[dst] = (uint8_t)lo;
         }
-        __syncthreads();
-        const int npad = L.npad;
-        for (int q = tid; q < npad; q += kBitsThreads) {
-          const uint16_t s = L.tdoc[q];
-          const int id = s == 0xFFFF ? 0 : (L.h.ent[s].y & kBitsIdMask);
-          L.tdoc[q] = (uint16_t)id;
-          if (id) atomicOr(reinterpret_cast<unsigned long long *>(&L.d.db.D[id]), 1ull << L.tsen[q]);
+        const uint64_t nb = __ballot(fresh);
+        if (nb) {
+          const int lead = __builtin_ctzll(nb);
+          int base = 0;
+          if (lane == lead) base = atomicAdd(&L.nlid, __popcll(nb));
+          base = __builtin_amdgcn_readlane(base, lead);
+          if (fresh) atomicOr(&L.ent[h].y, 1 + base + __popcll(nb & ((1ull << lane) - 1)));  // keeps a mark
         }
-        __syncthreads();
+      }
+      __syncthreads();
+      const int npad = L.npad;
+      for (int q = tid; q < npad; q += kBitsThreads) {
+        const uint16_t s = L.tdoc[q];
+        const int id = s == 0xFFFF ? 0 : (L.ent[s].y & kBitsIdMask);
+        L.tdoc[q] = (uint16_t)id;
+        if (id) atomicOr(reinterpret_cast<unsigned long long *>(&L.D[id]), 1ull << L.w.tsen[q]);
+      }
+      __syncthreads();  // the hash, D and the staged ids are complete; W is free
+      const int bmax = L.bmax;
 
-        const int jj = lane;  // this lane's sentence in the scoring stage
-        const bool jok = jj < nj;
-        const int bj = jok ? L.tlen[jj] : 0;
-        const int c = j0 + jj;
-        const bool narrow = amax < 64 && L.bmax < 64;
+      const int jj = lane;  // this lane's sentence in the scoring stage
+      const bool jok = jj < nj;
+      const int bj = jok ? L.tlen[jj] : 0;
+      const int c = j0 + jj;
+      for (int sx = 0, r0 = it.i0; r0 < it.i1; sx++, r0 += 64) {
+        const int R = min(64, n - r0);
+        float *const strip = a.S + it.s_off + (int64_t)(r0 >> 6) * (m + 63) * 64;
+        int64_t sb = sbv[0];
+        int al = alv[0];
+#pragma unroll
+        for (int k = 1; k < 4; k++)
+          if (sx == k) {
+            sb = sbv[k];
+            al = alv[k];
+          }
+        const int amax = __builtin_amdgcn_readfirstlane(wave_max(al));
+        const bool narrow = amax < 64 && bmax < 64;
+        // the source pass's first records travel while B is cleared
+        int4 ra[NR];
+        bits_s_fetch<NR>(a, sb, al, narrow ? wv : 0, narrow ? kBitsWaves : 1, 0, ra);
+        {
+          uint4 *b4 = reinterpret_cast<uint4 *>(L.w.B);
+          for (int s = tid; s < (TC + 2) / 2; s += kBitsThreads) b4[s] = make_uint4(0u, 0u, 0u, 0u);
+        }
+        __syncthreads();
         if (narrow) {
           uint32_t slo[kBitsNarrow] = {}, shi[kBitsNarrow] = {}, tlo[kBitsNarrow] = {}, thi[kBitsNarrow] = {};
-          bits_s_pass<kBitsNarrow, TC, BitsHash<TC>::kGroups>(a, L, sb, al, amax, wv, kBitsWaves, slo, shi);
-          __syncthreads();  // B complete; the hash is no longer read
-          uint64_t *xs_s = L.h.xch, *xs_t = L.h.xch + (kBitsWaves - 1) * kBitsNarrow * 64;
-          if (wv > 0) bits_store<kBitsNarrow>(xs_s + (wv - 1) * kBitsNarrow * 64, slo, shi);
+          bits_s_pass<kBitsNarrow, TC, BitsHash<TC>::kGroups>(a, L, sb, al, amax, wv, kBitsWaves, ra, slo, shi);
+          __syncthreads();  // B complete
           bits_t_pass<kBitsNarrow>(L, nj, 4 * wv, 4 * kBitsWaves, tlo, thi);
-          if (wv != 1) bits_store<kBitsNarrow>(xs_t + (wv == 0 ? 0 : wv - 1) * kBitsNarrow * 64, tlo, thi);
-          __syncthreads();  // partial counters in place; D and B no longer read
+          __syncthreads();  // B no longer read: W takes the partial counters
+          // W: source partials of waves 1-3 at 0, 1, 2 kPl; target partials of waves 0, 2, 3 at 3, 4, 5 kPl
+          uint64_t *const xs_s = L.w.xch, *const xs_t = L.w.xch + (kBitsWaves - 1) * kPl;
+          if (wv > 0) bits_store<kBitsNarrow>(xs_s + (wv - 1) * kPl, slo, shi);
+          if (wv != 1) bits_store<kBitsNarrow>(xs_t + (wv == 0 ? 0 : wv - 1) * kPl, tlo, thi);
+          __syncthreads();
+          // each sum goes where its wave read its own first partial set: summed m_s
+          // (lane = row) at 0, m_t (lane = sentence) at 3 kPl
+          uint64_t *const comb_s = L.w.xch, *const fin_t = xs_t, *const fin_s = L.w.xch + kPl;
           if (wv == 0) {
             for (int w = 0; w < kBitsWaves - 1; w++) {
               uint32_t ql[kBitsNarrow], qh[kBitsNarrow];
-              bits_load<kBitsNarrow>(xs_s + w * kBitsNarrow * 64, ql, qh);
+              bits_load<kBitsNarrow>(xs_s + w * kPl, ql, qh);
               bits_add_counters<kBitsNarrow>(slo, ql);
               bits_add_counters<kBitsNarrow>(shi, qh);
             }
@@ -1979,14 +2018,15 @@ __global__ __launch_bounds__(kBitsThreads, TC <= 1280 ? 3 : 2) void sim_bits_ker
           } else if (wv == 1) {
             for (int w = 0; w < kBitsWaves - 1; w++) {
               uint32_t ql[kBitsNarrow], qh[kBitsNarrow];
-              bits_load<kBitsNarrow>(xs_t + w * kBitsNarrow * 64, ql, qh);
+              bits_load<kBitsNarrow>(xs_t + w * kPl, ql, qh);
               bits_add_counters<kBitsNarrow>(tlo, ql);
               bits_add_counters<kBitsNarrow>(thi, qh);
             }
             bits_store<kBitsNarrow>(fin_t, tlo, thi);
           }
           __syncthreads();
-          // transpose m_s: wave w takes planes w and w + 4
+          // transpose m_s (lane = sentence) into the consumed partials of wave 2:
+          // wave w takes planes w and w + 4
           for (int p = wv; p < kBitsNarrow; p += kBitsWaves) {
             const uint64_t v = comb_s[p * 64 + lane];
             uint32_t vl = (uint32_t)v, vh = (uint32_t)(v >> 32);
@@ -1999,6 +2039,7 @@ __global__ __launch_bounds__(kBitsThreads, TC <= 1280 ? 3 : 2) void sim_bits_ker
           uint32_t sl[kBitsNarrow], sh[kBitsNarrow], tl[kBitsNarrow], th[kBitsNarrow];
           bits_load<kBitsNarrow>(fin_s, sl, sh);
           bits_load<kBitsNarrow>(fin_t, tl, th);
+          __syncthreads();  // the counters are in registers: W takes the scores
           float sv[16];
 #pragma unroll
           for (int g = 0; g < 4; g++) {
@@ -2023,24 +2064,33 @@ __global__ __launch_bounds__(kBitsThreads, TC <= 1280 ? 3 : 2) void sim_bits_ker
               }
             }
           }
+          // the scores go out by anti-diagonal through W (lane = row), so each
+          // store writes consecutive slots of the strip
+          float *const stage = L.w.stage;
 #pragma unroll
           for (int g = 0; g < 4; g++) {
 #pragma unroll
-            for (int k = 0; k < 4; k++) {
-              const int r = 32 * (g >> 1) + 2 * wv + (g & 1) + 8 * k;
-              if (jok && r < R) strip[(r + c) * R + r] = sv[4 * g + k];
-            }
+            for (int k = 0; k < 4; k++) stage[jj + 66 * (32 * (g >> 1) + 2 * wv + (g & 1) + 8 * k)] = sv[4 * g + k];
+          }
+          __syncthreads();
+          for (int d = wv; d < nj + R - 1; d += kBitsWaves) {
+            const int jl = d - lane;  // this lane's sentence on the diagonal
+            if (lane < R && jl >= 0 && jl < nj) strip[(int64_t)(j0 + d) * R + lane] = stage[jl + 66 * lane];
           }
         } else {
           // sentences of more than 63 tokens: one wave counts, in 11 planes
+          uint64_t *const fin_s = L.w.fin, *const fin_t = L.w.fin + kBitsWide * 64;
           if (wv == 0) {
             uint32_t slo[kBitsWide] = {}, shi[kBitsWide] = {}, tlo[kBitsWide] = {}, thi[kBitsWide] = {};
-            bits_s_pass<kBitsWide, TC, 1>(a, L, sb, al, amax, 0, 1, slo, shi);
+            int4 r4[4];
+#pragma unroll
+            for (int k = 0; k < 4; k++) r4[k] = ra[k];
+            bits_s_pass<kBitsWide, TC, 1>(a, L, sb, al, amax, 0, 1, r4, slo, shi);
             wave_sync();
             bits_t_pass<kBitsWide>(L, nj, 0, 4, tlo, thi);
 #pragma unroll
             for (int p = 0; p < kBitsWide; p++) bits_transpose64(slo[p], shi[p], lane);
-            wave_sync();  // D and B reads done before the region is overwritten
+            wave_sync();  // B reads done before W is overwritten
             bits_store<kBitsWide>(fin_s, slo, shi);
             bits_store<kBitsWide>(fin_t, tlo, thi);
           }
@@ -2069,9 +2119,9 @@ __global__ __launch_bounds__(kBitsThreads, TC <= 1280 ? 3 : 2) void sim_bits_ker
             }
           }
         }
-        __syncthreads();  // the chunk's LDS is reused by the next one
-        j0 = j1;
+        __syncthreads();  // W is cleared for the next strip; the hash and D for the next chunk
       }
+      j0 = j1;
     }
   }
 }
