@@ -2305,7 +2305,6 @@ __device__ __forceinline__ void nw_steps(const float (&buf)[kNwUnroll], float rb
   for (int k = 0; k < kNwUnroll; k++) {
     const int t = t0 + k;
     if (kTail && t > tend) break;
-    const float from_left_lane = shift_up_one_lane(L.h);
     float up0;
     if (kTop) {
       L.topv = __fadd_rn(L.topv, g);  // H[0][t] (starts at -g: -g + g = +0 at t = 0)
@@ -2313,7 +2312,10 @@ __device__ __forceinline__ void nw_steps(const float (&buf)[kNwUnroll], float rb
     } else {
       up0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(rbv), k));
     }
-    const float up = lane == 0 ? up0 : from_left_lane;
+    // lane l takes lane l - 1's H (wave_shr:1); lane 0, with no lane below
+    // it, keeps the DPP's old value, the row above the strip
+    const float up =
+        __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(up0), __float_as_int(L.h), 0x138, 0xF, 0xF, false));
     const float dd = __fadd_rn(L.upv, buf[k]);
     const float uu = __fadd_rn(up, g);
     const float ll = __fadd_rn(L.h, g);
