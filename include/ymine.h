@@ -150,7 +150,10 @@ typedef struct {
 
 /* ------------------------------------------------------------ batch mining */
 
-/* Mine a host-resident batch; the result is allocated by the library
+/* Mine a host-resident batch (Section 4: per document pair, the classifier
+ * scores every sentence pair, the score matrix is aligned with
+ * Needleman-Wunsch, and aligned pairs at or above the threshold are kept);
+ * the result is allocated by the library
  * (ym_result_free).  Internally: copy to HBM, similarity kernel, NW kernel
  * with device traceback and threshold, device compaction, copy back.  Large
  * batches are processed in chunks that fit the context's arena.  All-or-
@@ -241,13 +244,17 @@ ym_status ym_mine_device_static(ym_ctx *ctx, const ym_lexicon *lex, const ym_dev
 
 /* --------------------------------------------------- parity / debug entries */
 
-/* Similarity kernel alone on a host batch: S, m_s, m_t of every pair, row-
+/* Similarity kernel alone on a host batch (Section 4: the classifier's
+ * confidence for each sentence pair, from lexicon-overlap and length
+ * features): S, m_s, m_t of every pair, row-
  * major n x m, pairs back to back in batch order (sum of n*m entries each).
  * m_s / m_t may be NULL. */
 ym_status ym_similarity(ym_ctx *ctx, const ym_lexicon *lex, const ym_batch *batch, const ym_params *params,
                         float *S, int32_t *m_s, int32_t *m_t);
 
-/* NW kernel alone, fed score matrices from the host: pair p has n[p] x m[p]
+/* NW kernel alone (Section 4: the alignment of a document pair's score
+ * matrix with a gap penalty, then the threshold on the aligned pairs), fed
+ * score matrices from the host: pair p has n[p] x m[p]
  * scores at S + sum_{q<p} n[q]*m[q].  Outputs: align_score [n_pairs];
  * moves (may be NULL): pair p's forward path as 'D'/'U'/'L' bytes at offset
  * sum_{q<p} (n[q]+m[q]) with n_moves[p] entries; *out: accepted pairs. */
@@ -363,7 +370,9 @@ typedef struct {
   int32_t use_graph;          /* capture each step (copy-in, kernels, copy-out) in a hipGraph, updated in place between steps */
 } ym_server_opts;
 
-/* Start a serving loop over a resident lexicon and fixed parameters.  A
+/* Start a serving loop over a resident lexicon and fixed parameters
+ * (document pairs are mined independently of each other, Section 4, so
+ * pairs that arrive apart can share a batch step).  A
  * background thread admits submitted requests as slots and HBM budget free
  * up, packs them into the next batch step and runs the same kernels as
  * ym_mine; requests that arrive while a step runs join a later step. */
