@@ -1530,9 +1530,10 @@ constexpr int kBitsWide = 11;   // planes for counts <= 2047 (sentences of at mo
 template <int TC>
 struct BitsHash {
   static constexpr uint32_t kNB = TC;
-  // groups of four source positions per iteration of the source pass (the
-  // larger chunk size runs two workgroups per CU, with registers to spare)
-  static constexpr int kGroups = TC >= 2048 ? 2 : 1;
+  // groups of four source positions per iteration of the source pass (one:
+  // with the chunk's hash and D kept over an item's strips, two groups left
+  // the larger chunk size short of registers)
+  static constexpr int kGroups = 1;
 };
 template <int TC>
 struct BitsLds {
