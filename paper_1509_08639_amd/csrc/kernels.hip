@@ -2701,7 +2701,7 @@ __device__ __forceinline__ void nw_report_failed(const NwArgs &a, int64_t p) {
 // NPW pairs per workgroup, one wave each (waves never synchronise with each
 // other).  Large pairs (nw_is_big) are left to nw_big_kernel.
 template <int NPW>
-__global__ __launch_bounds__(64 * NPW) void nw_kernel(NwArgs a0) {
+__global__ __launch_bounds__(64 * NPW, 4) void nw_kernel(NwArgs a0) {
   const NwArgs a = nw_gap_view(a0);
   __shared__ uint32_t sdir_all[NPW][kDirLds];
   __shared__ float srow_all[NPW][kRowLds];

@@ -29,7 +29,7 @@ constexpr int kTabLen = 64;             // score table covers sentence lengths <
 constexpr int kLogTabLen = 6;
 
 // NW kernel staging.
-constexpr int kDirLds = 2816;           // direction words held in LDS (covers 200 x 200)
+constexpr int kDirLds = 1856;           // direction words held in LDS (covers 168 x 160; 9.25 KB with the row, four waves per SIMD)
 constexpr int kRowLds = 512;            // boundary-row floats held in LDS
 
 static_assert((1 << kLogUcap) == kUcap, "hash capacity");

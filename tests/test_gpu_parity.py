@@ -149,6 +149,8 @@ def _nw_cases():
     r = np.random.default_rng(5)
     mats = []
     for (n, m) in [(1, 1), (0, 5), (6, 0), (0, 0), (3, 7), (64, 64), (65, 63), (127, 129), (200, 200),
+                   # the last pair whose direction codes fit in LDS, and the first that does not
+                   (168, 160), (169, 160),
                    (40, 45), (300, 17), (17, 300), (130, 600), (70, 520), (1000, 1100),
                    # pipelined sweep of large pairs: 8 strips (last of one row), 8 full, 17 strips
                    # (more strips than waves), a single target column, no target sentence
